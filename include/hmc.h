@@ -1,0 +1,193 @@
+/*
+ * hmc.h -- C interface of the MI355X (gfx950) library for the parallel
+ * adaptive Metropolis sweeps of a classical Heisenberg spin lattice
+ * (Lepadatu et al., arXiv:2103.03517).
+ *
+ * The library updates a simple-cubic, fully periodic lattice of unit spins
+ * with the spin Hamiltonian of Eq. 2 (nearest-neighbour exchange J,
+ * uniaxial anisotropy Ku along eu, cubic anisotropy Kc with the Cartesian
+ * axes as easy axes for Kc > 0, Zeeman field h), in reduced units: J is
+ * the energy unit, k_B = 1 and the moment mu0*mu_S is folded into h.
+ *
+ * Ownership and threading:
+ *   - the caller owns one device workspace of hmc_workspace_bytes() bytes
+ *     (for example a torch uint8 tensor) that must outlive the handle;
+ *     the library keeps the spins, the cone angle, the sweep counter and
+ *     the accumulators there and never allocates device memory itself;
+ *   - the library allocates only the small host-side handle, released by
+ *     hmc_destroy();
+ *   - all work is enqueued on the HIP stream given at hmc_init_lattice();
+ *     hmc_sweep() and hmc_constrained_sweep() return without waiting;
+ *     hmc_observables(), hmc_copy_spins(), hmc_get_state(),
+ *     hmc_set_state() and hmc_read_timing() synchronise that stream;
+ *   - one handle must not be used from two threads at once; different
+ *     handles are independent.
+ *
+ * Every function returns an hmc_status (0 on success, negative on error)
+ * unless stated otherwise; nothing aborts or throws.  After an error,
+ * hmc_last_error() gives a message for the handle involved.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
+ * (seed low word, seed high word) and counter (sweep, id, tag, instance);
+ * tag 0/1 = standard update of a red/black site (id = site id
+ * x + nx*(y + ny*z)), 2/3 = constrained pair move of colour 0/1 (id = pair
+ * index), 4 = random initial spin (sweep word 0), 5/6 = Feistel keys of
+ * the colour-0/1 shuffle (id 0).  Results therefore do not depend on the
+ * launch configuration.
+ */
+#ifndef HMC_H
+#define HMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HMC_OK = 0,
+    HMC_EINVAL = -1,    /* a null pointer, a non-finite or out-of-range value */
+    HMC_EDIM = -2,      /* lattice dimensions not even, below 2, or too large */
+    HMC_ENOMEM = -3,    /* workspace too small or misaligned */
+    HMC_EHIP = -4,      /* a HIP runtime call failed */
+    HMC_ESTATE = -5,    /* state buffer of the wrong size or for another lattice */
+    HMC_ENUMERIC = -6   /* a non-finite value appeared in the reductions */
+} hmc_status;
+
+typedef struct hmc_lattice hmc_lattice;
+
+/* Lattice and model parameters (Eq. 2, Sec. 3 of the paper). */
+typedef struct {
+    int32_t  nx, ny, nz;    /* each even and >= 2 (the red/black colouring of a
+                               periodic axis needs an even length, Sec. 2);
+                               nx*ny*nz < 2^32 */
+    int32_t  precision;     /* 32: FP32 spins and energy changes, FP64 sums;
+                               64: FP64 throughout */
+    double   J;             /* exchange (energy unit) */
+    double   Ku;            /* uniaxial anisotropy constant */
+    double   eu[3];         /* uniaxial easy axis, normalised inside; non-zero */
+    double   Kc;            /* cubic anisotropy constant */
+    double   h[3];          /* Zeeman field mu0*mu_S*H_a in energy units */
+    uint64_t seed;          /* Philox key */
+    uint32_t instance;      /* fourth Philox counter word */
+    int32_t  init;          /* 0: every spin along init_dir; 1: uniform on the sphere */
+    double   init_dir[3];   /* non-zero when init == 0 */
+    int32_t  theta0_deg;    /* initial cone angle, 1..180 degrees */
+} hmc_params;
+
+/* Observables.  The instantaneous values describe the spins at the time of
+ * the call; the averages cover the sampled sweeps since the last
+ * hmc_reset_stats().  Index alpha of the 4-arrays: 0 = l (|m|), 1 = x,
+ * 2 = y, 3 = z, with m = M/N the spatially averaged moment (Eq. 6). */
+typedef struct {
+    int64_t n;              /* number of spins N */
+    int64_t sweeps_done;    /* global sweep counter */
+    int64_t samples;        /* sampled sweeps since the last reset */
+    int64_t torque_samples; /* of which constrained sweeps */
+    int64_t accepted_last;  /* accepted updates of the last sweep (a pair counts 2) */
+    int32_t theta_deg;      /* current cone angle */
+    int32_t precision;
+    double  M[3];           /* sum_i S_i */
+    double  m;              /* |M| / N */
+    double  E;              /* total energy, every bond counted once */
+    double  E_exch, E_uni, E_cub, E_zee;
+    double  torque[3];      /* sum_i S_i x (-dE_anis/dS_i) */
+    double  mean_m[4];      /* <m_alpha> */
+    double  var_m[4];       /* <m_alpha^2> - <m_alpha>^2 */
+    double  mean_E;         /* <E>/N */
+    double  var_E;          /* variance of E/N */
+    double  mean_Eanis;     /* <E_uni + E_cub>/N */
+    double  mean_torque[3]; /* <torque>/N over the constrained samples */
+    double  chi[4];         /* N var(m_alpha) / T, Eq. 6 with mu_S = k_B = 1 */
+    double  T_sample;       /* temperature of the last sampled sweep */
+} hmc_obs;
+
+/* Per-kernel timing collected with HIP events on the handle's stream while
+ * timing is enabled.  Kinds: 0 = standard colour pass, 1 = constrained
+ * pair pass, 2 = per-sweep finalize (reductions, cone angle),
+ * 3 = other (initialisation, measurement). */
+typedef struct {
+    int64_t count[4];
+    double  total_ms[4];
+} hmc_timing;
+
+/* Size in bytes of the device workspace for these parameters, 0 if the
+ * parameters are invalid. */
+size_t hmc_workspace_bytes(const hmc_params* p);
+
+/* Validates p, lays the lattice out in dev_ws (device memory, 256-byte
+ * aligned, at least hmc_workspace_bytes(p) bytes, owned by the caller)
+ * and enqueues the initial state (init == 0: along init_dir; init == 1:
+ * uniform on the sphere from Philox tag 4) on hip_stream (a hipStream_t,
+ * NULL for the default stream).  On success *out receives the handle.
+ * Errors: HMC_EINVAL, HMC_EDIM, HMC_ENOMEM, HMC_EHIP. */
+int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes,
+                     void* hip_stream, hmc_lattice** out);
+
+/* Enqueues n_sweeps (>= 0) iterations of the parallel Metropolis algorithm
+ * of Table A1 at temperature T (> 0, finite): a red pass, a black pass
+ * (each site: cone move uniform in solid angle within the current cone
+ * angle, accepted when P < exp(-dE/T), Eq. 1, with dE from Eq. 2), then
+ * the cone angle moves one degree toward an acceptance rate of 1/2.  If
+ * sample != 0 every sweep adds m_alpha, E, E_anis to the accumulators
+ * (Eq. 6).  Errors: HMC_EINVAL, HMC_EHIP. */
+int hmc_sweep(hmc_lattice* L, double T, int32_t n_sweeps, int32_t sample);
+
+/* Enqueues n_sweeps iterations of the parallel constrained algorithm of
+ * Table A2 with constraint direction eC (non-zero, normalised inside):
+ * M_L = sum_i S_i . eC taken once at the start of each sweep, each colour
+ * shuffled by a keyed permutation, consecutive shuffled spins paired, the
+ * second spin of a pair compensating the first one's transverse change,
+ * and the pair accepted when P < (M_L'/M_L)^2 |S_j.eC / S_j'.eC|
+ * exp(-dE/T).  A pair with no real compensating spin, or whose new M_L
+ * would not be positive, is rejected.  Sampled sweeps also accumulate the
+ * anisotropy torque.  Errors: HMC_EINVAL, HMC_EHIP. */
+int hmc_constrained_sweep(hmc_lattice* L, double T, const double eC[3],
+                          int32_t n_sweeps, int32_t sample);
+
+/* Measures the current spins and copies counters and accumulators into
+ * *out (synchronises).  Returns HMC_ENUMERIC (with *out filled) if a
+ * non-finite value was met in any reduction since the lattice was set. */
+int hmc_observables(hmc_lattice* L, hmc_obs* out);
+
+/* Clears the accumulators (not the spins, cone angle or sweep counter). */
+int hmc_reset_stats(hmc_lattice* L);
+
+/* Copies the spins between the device and host_xyz, an array of 3*N
+ * doubles in AoS order S[3*i + a] with site id i = x + nx*(y + ny*z).
+ * to_host != 0: device -> host; else host -> device (FP32 lattices round
+ * to nearest).  Synchronises. */
+int hmc_copy_spins(hmc_lattice* L, double* host_xyz, int32_t to_host);
+
+/* Checkpoint: hmc_state_bytes() gives the size of a state image (spins,
+ * cone angle, sweep counter, accumulators and the parameters it belongs
+ * to); get/set copy it to/from host memory.  Because the random numbers
+ * are counter-based, a restored lattice continues bit for bit.
+ * hmc_set_state returns HMC_ESTATE for an image of another lattice. */
+size_t hmc_state_bytes(const hmc_lattice* L);
+int hmc_get_state(hmc_lattice* L, void* host_buf, size_t bytes);
+int hmc_set_state(hmc_lattice* L, const void* host_buf, size_t bytes);
+
+/* Launch shape of the standard pass: each work-group of 256 threads
+ * covers 256*sites_per_thread in-plane sites of one colour and marches
+ * over z_chunk planes.  sites_per_thread in {1, 2, 4}; z_chunk in
+ * [1, 1024].  The spins produced do not depend on the shape (random
+ * numbers are keyed by site); reduction orders, and so the last bits of
+ * the observables, do.  Errors: HMC_EINVAL. */
+int hmc_set_launch(hmc_lattice* L, int32_t sites_per_thread, int32_t z_chunk);
+int hmc_get_launch(const hmc_lattice* L, int32_t* sites_per_thread, int32_t* z_chunk);
+
+/* Per-kernel timing (see hmc_timing).  Enabling resets the totals;
+ * hmc_read_timing synchronises and returns the totals so far. */
+int hmc_set_timing(hmc_lattice* L, int32_t enable);
+int hmc_read_timing(hmc_lattice* L, hmc_timing* out);
+
+void hmc_destroy(hmc_lattice* L);
+const char* hmc_strerror(int status);
+const char* hmc_last_error(const hmc_lattice* L);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

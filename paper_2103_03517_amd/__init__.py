@@ -1,0 +1,248 @@
+"""Python binding of the MI355X library for the parallel Metropolis sweeps of a
+classical Heisenberg spin lattice (Lepadatu et al., arXiv:2103.03517).
+
+Argument marshalling only: every step of the sweeps runs in the HIP kernels of
+libhmc.so (built from csrc/ for gfx950).  PyTorch supplies the device
+workspace and the stream.  The library must be built (``__graft_entry__.build``)
+before use; there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+__all__ = ["Lattice", "HmcError", "lib", "LIB_PATH", "SYMBOLS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmc.so")
+
+# status codes of include/hmc.h
+OK, EINVAL, EDIM, ENOMEM, EHIP, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("J", ctypes.c_double), ("Ku", ctypes.c_double), ("eu", ctypes.c_double * 3),
+        ("Kc", ctypes.c_double), ("h", ctypes.c_double * 3),
+        ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32),
+        ("init", ctypes.c_int32), ("init_dir", ctypes.c_double * 3),
+        ("theta0_deg", ctypes.c_int32),
+    ]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("sweeps_done", ctypes.c_int64), ("samples", ctypes.c_int64),
+        ("torque_samples", ctypes.c_int64), ("accepted_last", ctypes.c_int64),
+        ("theta_deg", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("M", ctypes.c_double * 3), ("m", ctypes.c_double), ("E", ctypes.c_double),
+        ("E_exch", ctypes.c_double), ("E_uni", ctypes.c_double), ("E_cub", ctypes.c_double),
+        ("E_zee", ctypes.c_double), ("torque", ctypes.c_double * 3),
+        ("mean_m", ctypes.c_double * 4), ("var_m", ctypes.c_double * 4),
+        ("mean_E", ctypes.c_double), ("var_E", ctypes.c_double), ("mean_Eanis", ctypes.c_double),
+        ("mean_torque", ctypes.c_double * 3), ("chi", ctypes.c_double * 4),
+        ("T_sample", ctypes.c_double),
+    ]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
+
+
+TIMING_KINDS = ("pass", "pair_pass", "finalize", "other")
+
+# every function declared in include/hmc.h
+SYMBOLS = ("hmc_workspace_bytes", "hmc_init_lattice", "hmc_sweep", "hmc_constrained_sweep",
+           "hmc_observables", "hmc_reset_stats", "hmc_copy_spins", "hmc_state_bytes",
+           "hmc_get_state", "hmc_set_state", "hmc_set_launch", "hmc_get_launch",
+           "hmc_set_timing", "hmc_read_timing", "hmc_destroy", "hmc_strerror",
+           "hmc_last_error")
+
+_lib = None
+
+
+def lib():
+    """Load libhmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    P = ctypes.POINTER
+    L.hmc_workspace_bytes.restype = ctypes.c_size_t
+    L.hmc_workspace_bytes.argtypes = [P(Params)]
+    L.hmc_init_lattice.restype = i32
+    L.hmc_init_lattice.argtypes = [P(Params), vp, ctypes.c_size_t, vp, P(vp)]
+    L.hmc_sweep.restype = i32
+    L.hmc_sweep.argtypes = [vp, dbl, i32, i32]
+    L.hmc_constrained_sweep.restype = i32
+    L.hmc_constrained_sweep.argtypes = [vp, dbl, P(dbl), i32, i32]
+    L.hmc_observables.restype = i32
+    L.hmc_observables.argtypes = [vp, P(Obs)]
+    L.hmc_reset_stats.restype = i32
+    L.hmc_reset_stats.argtypes = [vp]
+    L.hmc_copy_spins.restype = i32
+    L.hmc_copy_spins.argtypes = [vp, P(dbl), i32]
+    L.hmc_state_bytes.restype = ctypes.c_size_t
+    L.hmc_state_bytes.argtypes = [vp]
+    L.hmc_get_state.restype = i32
+    L.hmc_get_state.argtypes = [vp, vp, ctypes.c_size_t]
+    L.hmc_set_state.restype = i32
+    L.hmc_set_state.argtypes = [vp, vp, ctypes.c_size_t]
+    L.hmc_set_launch.restype = i32
+    L.hmc_set_launch.argtypes = [vp, i32, i32]
+    L.hmc_get_launch.restype = i32
+    L.hmc_get_launch.argtypes = [vp, P(i32), P(i32)]
+    L.hmc_set_timing.restype = i32
+    L.hmc_set_timing.argtypes = [vp, i32]
+    L.hmc_read_timing.restype = i32
+    L.hmc_read_timing.argtypes = [vp, P(Timing)]
+    L.hmc_destroy.restype = None
+    L.hmc_destroy.argtypes = [vp]
+    L.hmc_strerror.restype = ctypes.c_char_p
+    L.hmc_strerror.argtypes = [i32]
+    L.hmc_last_error.restype = ctypes.c_char_p
+    L.hmc_last_error.argtypes = [vp]
+    _lib = L
+    return L
+
+
+class HmcError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"hmc status {status}: {message}")
+        self.status = status
+
+
+def make_params(nx, ny, nz, precision=64, J=1.0, Ku=0.0, eu=(0.0, 0.0, 1.0), Kc=0.0,
+                h=(0.0, 0.0, 0.0), seed=1, instance=0, init="aligned", init_dir=(0.0, 0.0, 1.0),
+                theta0_deg=30):
+    p = Params()
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    p.precision = int(precision)
+    p.J, p.Ku, p.Kc = float(J), float(Ku), float(Kc)
+    p.eu[:] = [float(v) for v in eu]
+    p.h[:] = [float(v) for v in h]
+    p.seed = int(seed)
+    p.instance = int(instance)
+    p.init = {"aligned": 0, "random": 1}[init] if isinstance(init, str) else int(init)
+    p.init_dir[:] = [float(v) for v in init_dir]
+    p.theta0_deg = int(theta0_deg)
+    return p
+
+
+def workspace_bytes(params):
+    return int(lib().hmc_workspace_bytes(ctypes.byref(params)))
+
+
+def _obs_dict(o):
+    d = {}
+    for name, _ in Obs._fields_:
+        v = getattr(o, name)
+        d[name] = [float(x) for x in v] if hasattr(v, "__len__") else v
+    return d
+
+
+class Lattice:
+    """One spin lattice resident in a torch-owned device workspace."""
+
+    def __init__(self, nx, ny, nz, device="cuda", stream=None, **kw):
+        self._lib = lib()
+        self.params = make_params(nx, ny, nz, **kw)
+        self.shape = (int(nx), int(ny), int(nz))
+        self.n = int(nx) * int(ny) * int(nz)
+        nbytes = workspace_bytes(self.params)
+        if nbytes == 0:
+            h = ctypes.c_void_p()
+            st = self._lib.hmc_init_lattice(ctypes.byref(self.params), None, 0, None, ctypes.byref(h))
+            raise HmcError(st, self._lib.hmc_strerror(st).decode())
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = self._lib.hmc_init_lattice(ctypes.byref(self.params),
+                                        ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != OK:
+            raise HmcError(st, self._lib.hmc_strerror(st).decode())
+        self._h = h
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, st):
+        if st != OK:
+            raise HmcError(st, self._lib.hmc_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the method --------------------------------------------------------
+    def sweep(self, T, n=1, sample=False):
+        self._check(self._lib.hmc_sweep(self._h, float(T), int(n), int(bool(sample))))
+
+    def constrained_sweep(self, T, eC, n=1, sample=False):
+        e = (ctypes.c_double * 3)(*[float(v) for v in eC])
+        self._check(self._lib.hmc_constrained_sweep(self._h, float(T), e, int(n), int(bool(sample))))
+
+    def observables(self, check=True):
+        o = Obs()
+        st = self._lib.hmc_observables(self._h, ctypes.byref(o))
+        if check:
+            self._check(st)
+        d = _obs_dict(o)
+        d["status"] = st
+        return d
+
+    def reset_stats(self):
+        self._check(self._lib.hmc_reset_stats(self._h))
+
+    # -- data movement -----------------------------------------------------
+    def spins(self):
+        out = np.empty((self.n, 3), dtype=np.float64)
+        self._check(self._lib.hmc_copy_spins(
+            self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1))
+        return out
+
+    def set_spins(self, S):
+        a = np.ascontiguousarray(np.asarray(S, dtype=np.float64).reshape(self.n, 3))
+        self._check(self._lib.hmc_copy_spins(
+            self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0))
+
+    def get_state(self):
+        n = int(self._lib.hmc_state_bytes(self._h))
+        buf = (ctypes.c_char * n)()
+        self._check(self._lib.hmc_get_state(self._h, buf, n))
+        return bytes(buf)
+
+    def set_state(self, blob):
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        self._check(self._lib.hmc_set_state(self._h, buf, len(blob)))
+
+    # -- launch shape and timing ------------------------------------------
+    def set_launch(self, sites_per_thread, z_chunk):
+        self._check(self._lib.hmc_set_launch(self._h, int(sites_per_thread), int(z_chunk)))
+
+    def get_launch(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.hmc_get_launch(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
+    def set_timing(self, enable=True):
+        self._check(self._lib.hmc_set_timing(self._h, int(bool(enable))))
+
+    def read_timing(self):
+        t = Timing()
+        self._check(self._lib.hmc_read_timing(self._h, ctypes.byref(t)))
+        return {k: {"count": int(t.count[i]), "total_ms": float(t.total_ms[i])}
+                for i, k in enumerate(TIMING_KINDS)}

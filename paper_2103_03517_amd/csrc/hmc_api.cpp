@@ -1,0 +1,595 @@
+// hmc_api.cpp -- the C interface declared in include/hmc.h: parameter
+// validation, workspace layout, the per-sweep launch sequence, host<->device
+// copies, checkpoints and event timing.  All arithmetic of the method runs in
+// the kernels of hmc_kernels.hip.
+#include "hmc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "hmc_internal.h"
+
+using hmc::DevLattice;
+using hmc::DevState;
+
+namespace {
+
+constexpr uint32_t kStateMagic = 0x484D4331u;  // "HMC1"
+constexpr size_t kMaxEvents = 16384;           // timing event pairs before a flush
+
+struct Layout {
+    size_t pitch, off_state, off_c1, off_part, off_cnt, total;
+    int64_t max_blocks;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool finite3(const double v[3]) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+bool nonzero3(const double v[3]) { return v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0; }
+
+int validate(const hmc_params* p, char* msg, size_t n)
+{
+    if (!p) { snprintf(msg, n, "null parameter block"); return HMC_EINVAL; }
+    const int32_t d[3] = {p->nx, p->ny, p->nz};
+    for (int i = 0; i < 3; ++i)
+        if (d[i] < 2 || (d[i] & 1)) {
+            snprintf(msg, n, "lattice dimensions must be even and >= 2 (got %d x %d x %d)", p->nx, p->ny, p->nz);
+            return HMC_EDIM;
+        }
+    if (p->nx > 1024) { snprintf(msg, n, "nx must be <= 1024 (got %d)", p->nx); return HMC_EDIM; }
+    const uint64_t N = (uint64_t)p->nx * (uint64_t)p->ny * (uint64_t)p->nz;
+    if (N >= (1ull << 32)) { snprintf(msg, n, "nx*ny*nz must be < 2^32"); return HMC_EDIM; }
+    if (p->precision != 32 && p->precision != 64) {
+        snprintf(msg, n, "precision must be 32 or 64 (got %d)", p->precision);
+        return HMC_EINVAL;
+    }
+    if (!isfinite(p->J) || !isfinite(p->Ku) || !isfinite(p->Kc) || !finite3(p->eu) || !finite3(p->h)) {
+        snprintf(msg, n, "model constants must be finite");
+        return HMC_EINVAL;
+    }
+    if (!nonzero3(p->eu)) { snprintf(msg, n, "uniaxial axis eu must be non-zero"); return HMC_EINVAL; }
+    if (p->init != 0 && p->init != 1) { snprintf(msg, n, "init must be 0 or 1"); return HMC_EINVAL; }
+    if (p->init == 0 && (!finite3(p->init_dir) || !nonzero3(p->init_dir))) {
+        snprintf(msg, n, "init_dir must be finite and non-zero");
+        return HMC_EINVAL;
+    }
+    if (p->theta0_deg < 1 || p->theta0_deg > 180) {
+        snprintf(msg, n, "theta0_deg must be in [1, 180] (got %d)", p->theta0_deg);
+        return HMC_EINVAL;
+    }
+    return HMC_OK;
+}
+
+Layout layout_for(const hmc_params* p)
+{
+    Layout L{};
+    const uint64_t Nc = (uint64_t)p->nx * p->ny * p->nz / 2;
+    const size_t rs = p->precision / 8;
+    L.pitch = align_up(Nc * rs, hmc::kAlign);
+    size_t off = 6 * L.pitch;
+    L.off_state = off;
+    off += align_up(sizeof(DevState), hmc::kAlign);
+    L.off_c1 = off;
+    off += align_up(181 * sizeof(double) + 181 * sizeof(float), hmc::kAlign);
+    L.max_blocks = hmc::max_blocks_for(p->nx, p->ny, p->nz);
+    L.off_part = off;
+    off += align_up((size_t)L.max_blocks * hmc::kNumPart * sizeof(double), hmc::kAlign);
+    L.off_cnt = off;
+    off += align_up((size_t)L.max_blocks * 2 * sizeof(uint32_t), hmc::kAlign);
+    L.total = off;
+    return L;
+}
+
+struct StateHeader {
+    uint32_t magic, precision;
+    int32_t nx, ny, nz, pad;
+    uint64_t seed;
+    uint32_t instance, pad2;
+    double J, Ku, eu[3], Kc, h[3];
+};
+
+}  // namespace
+
+struct hmc_lattice {
+    DevLattice d;
+    hmc_params p;
+    hipStream_t stream;
+    Layout lay;
+    int spt = 2, zc = 16;
+    bool m_valid = false;
+    char err[256] = {0};
+    double c1d[181];
+    float c1f[181];
+    DevState init_state;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;      // start/stop pairs
+    std::vector<int> kind;
+    size_t used = 0;
+    hmc_timing tot{};
+};
+
+namespace {
+
+int fail(hmc_lattice* L, int status, const char* what, hipError_t e = hipSuccess)
+{
+    if (L) {
+        if (e != hipSuccess) snprintf(L->err, sizeof(L->err), "%s: %s", what, hipGetErrorString(e));
+        else snprintf(L->err, sizeof(L->err), "%s", what);
+    }
+    return status;
+}
+
+int flush_timing(hmc_lattice* L)
+{
+    if (L->used == 0) return HMC_OK;
+    hipError_t e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "hipStreamSynchronize", e);
+    for (size_t i = 0; i < L->used; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, L->ev[2 * i], L->ev[2 * i + 1]);
+        if (e != hipSuccess) return fail(L, HMC_EHIP, "hipEventElapsedTime", e);
+        L->tot.count[L->kind[i]] += 1;
+        L->tot.total_ms[L->kind[i]] += ms;
+    }
+    L->used = 0;
+    return HMC_OK;
+}
+
+// Runs one launch, bracketed by events on the lattice's stream when timing.
+template <class F>
+int launch(hmc_lattice* L, int kind, const char* what, F f)
+{
+    if (L->timing) {
+        if (L->used == kMaxEvents) {
+            int st = flush_timing(L);
+            if (st != HMC_OK) return st;
+        }
+        while (L->ev.size() < 2 * (L->used + 1)) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return fail(L, HMC_EHIP, "hipEventCreate", r);
+            L->ev.push_back(e);
+        }
+        L->kind.resize(L->used + 1);
+        hipError_t r = hipEventRecord(L->ev[2 * L->used], L->stream);
+        if (r != hipSuccess) return fail(L, HMC_EHIP, "hipEventRecord", r);
+    }
+    hipError_t e = f();
+    if (e != hipSuccess) return fail(L, HMC_EHIP, what, e);
+    if (L->timing) {
+        hipError_t r = hipEventRecord(L->ev[2 * L->used + 1], L->stream);
+        if (r != hipSuccess) return fail(L, HMC_EHIP, "hipEventRecord", r);
+        L->kind[L->used] = kind;
+        L->used += 1;
+    }
+    return HMC_OK;
+}
+
+int measure(hmc_lattice* L)
+{
+    int64_t nb = 0;
+    int st = launch(L, 3, "measure kernel", [&] { return hmc::launch_measure(L->d, L->stream, &nb); });
+    if (st != HMC_OK) return st;
+    st = launch(L, 3, "finalize kernel", [&] {
+        return hmc::launch_finalize(L->d, 0, 0, nb, hmc::kFinObs | hmc::kFinTorque, 0.0, L->stream);
+    });
+    if (st == HMC_OK) L->m_valid = true;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hmc_workspace_bytes(const hmc_params* p)
+{
+    char msg[128];
+    if (validate(p, msg, sizeof(msg)) != HMC_OK) return 0;
+    return layout_for(p).total;
+}
+
+int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, hmc_lattice** out)
+{
+    if (!out) return HMC_EINVAL;
+    *out = nullptr;
+    char msg[256];
+    int st = validate(p, msg, sizeof(msg));
+    if (st != HMC_OK) return st;
+    const Layout lay = layout_for(p);
+    if (!dev_ws || ws_bytes < lay.total || ((uintptr_t)dev_ws % hmc::kAlign) != 0) return HMC_ENOMEM;
+
+    hmc_lattice* L = new (std::nothrow) hmc_lattice();
+    if (!L) return HMC_ENOMEM;
+    L->p = *p;
+    L->stream = static_cast<hipStream_t>(hip_stream);
+    L->lay = lay;
+    const double eun = sqrt(p->eu[0] * p->eu[0] + p->eu[1] * p->eu[1] + p->eu[2] * p->eu[2]);
+    for (int a = 0; a < 3; ++a) L->p.eu[a] = p->eu[a] / eun;
+    if (p->init == 0) {
+        const double dn = sqrt(p->init_dir[0] * p->init_dir[0] + p->init_dir[1] * p->init_dir[1] +
+                               p->init_dir[2] * p->init_dir[2]);
+        for (int a = 0; a < 3; ++a) L->p.init_dir[a] = p->init_dir[a] / dn;
+    }
+
+    DevLattice& d = L->d;
+    char* base = static_cast<char*>(dev_ws);
+    d.precision = p->precision;
+    d.nx = p->nx;
+    d.ny = p->ny;
+    d.nz = p->nz;
+    d.hx = p->nx / 2;
+    d.P = d.hx * p->ny;
+    d.N = (int64_t)p->nx * p->ny * p->nz;
+    d.Nc = d.N / 2;
+    d.pitch = lay.pitch;
+    d.spins = base;
+    d.st = reinterpret_cast<DevState*>(base + lay.off_state);
+    d.c1tab = p->precision == 64 ? static_cast<const void*>(base + lay.off_c1)
+                                 : static_cast<const void*>(base + lay.off_c1 + 181 * sizeof(double));
+    d.part = reinterpret_cast<double*>(base + lay.off_part);
+    d.cnt = reinterpret_cast<uint32_t*>(base + lay.off_cnt);
+    d.max_blocks = lay.max_blocks;
+    d.J = p->J;
+    d.Ku = p->Ku;
+    d.Kc = p->Kc;
+    for (int a = 0; a < 3; ++a) {
+        d.eu[a] = L->p.eu[a];
+        d.h[a] = p->h[a];
+        d.init_dir[a] = L->p.init_dir[a];
+    }
+    d.key0 = (uint32_t)(p->seed & 0xFFFFFFFFu);
+    d.key1 = (uint32_t)(p->seed >> 32);
+    d.instance = p->instance;
+    d.init_mode = p->init;
+
+    // 1 - cos(theta) = 2 sin^2(theta/2) for theta = 0..180 degrees
+    for (int th = 0; th <= 180; ++th) {
+        const double s = sin((double)th * M_PI / 360.0);
+        L->c1d[th] = 2.0 * s * s;
+        L->c1f[th] = (float)L->c1d[th];
+    }
+    // default launch shape: 512 in-plane sites per work-group, 16 planes,
+    // narrowed to 256 sites when the LDS window would exceed 64 KiB
+    if (2 * 3 * (size_t)(hmc::kThreads * L->spt + 2 * d.hx) * (p->precision / 8) > 64 * 1024) L->spt = 1;
+    memset(&L->init_state, 0, sizeof(L->init_state));
+    L->init_state.theta = p->theta0_deg;
+
+    hipError_t e = hipMemcpyAsync(base + lay.off_c1, L->c1d, sizeof(L->c1d), hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + lay.off_c1 + 181 * sizeof(double), L->c1f, sizeof(L->c1f), hipMemcpyHostToDevice,
+                           L->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d.st, &L->init_state, sizeof(DevState), hipMemcpyHostToDevice, L->stream);
+    if (e != hipSuccess) { delete L; return HMC_EHIP; }
+    st = launch(L, 3, "init kernel", [&] { return hmc::launch_init(L->d, L->stream); });
+    if (st == HMC_OK) st = measure(L);
+    if (st == HMC_OK) e = hipStreamSynchronize(L->stream);
+    if (st != HMC_OK || e != hipSuccess) { delete L; return st != HMC_OK ? st : HMC_EHIP; }
+    *out = L;
+    return HMC_OK;
+}
+
+int hmc_sweep(hmc_lattice* L, double T, int32_t n_sweeps, int32_t sample)
+{
+    if (!L) return HMC_EINVAL;
+    if (!(T > 0.0) || !isfinite(T)) return fail(L, HMC_EINVAL, "temperature must be positive and finite");
+    if (n_sweeps < 0) return fail(L, HMC_EINVAL, "n_sweeps must be >= 0");
+    const bool obs = sample != 0;
+    for (int32_t it = 0; it < n_sweeps; ++it) {
+        int64_t nr = 0, nb = 0;
+        int st = launch(L, 0, "red pass", [&] {
+            return hmc::launch_pass(L->d, 0, false, L->spt, L->zc, T, L->stream, &nr);
+        });
+        if (st == HMC_OK)
+            st = launch(L, 0, "black pass", [&] {
+                return hmc::launch_pass(L->d, 1, obs, L->spt, L->zc, T, L->stream, &nb);
+            });
+        if (st == HMC_OK)
+            st = launch(L, 2, "finalize kernel", [&] {
+                const int fl = hmc::kFinCounts | (obs ? (hmc::kFinObs | hmc::kFinSample) : 0);
+                return hmc::launch_finalize(L->d, nr, nb, obs ? nb : 0, fl, T, L->stream);
+            });
+        if (st != HMC_OK) return st;
+        L->m_valid = obs;
+    }
+    return HMC_OK;
+}
+
+int hmc_constrained_sweep(hmc_lattice* L, double T, const double eC[3], int32_t n_sweeps, int32_t sample)
+{
+    if (!L) return HMC_EINVAL;
+    if (!(T > 0.0) || !isfinite(T)) return fail(L, HMC_EINVAL, "temperature must be positive and finite");
+    if (!eC || !finite3(eC) || !nonzero3(eC)) return fail(L, HMC_EINVAL, "eC must be finite and non-zero");
+    if (n_sweeps < 0) return fail(L, HMC_EINVAL, "n_sweeps must be >= 0");
+    const double n = sqrt(eC[0] * eC[0] + eC[1] * eC[1] + eC[2] * eC[2]);
+    const double e[3] = {eC[0] / n, eC[1] / n, eC[2] / n};
+    if (n_sweeps > 0 && !L->m_valid) {
+        int st = measure(L);
+        if (st != HMC_OK) return st;
+    }
+    for (int32_t it = 0; it < n_sweeps; ++it) {
+        int64_t nr = 0, nb = 0;
+        int st = launch(L, 1, "red pair pass", [&] { return hmc::launch_pair_pass(L->d, 0, e, T, L->stream, &nr); });
+        if (st == HMC_OK)
+            st = launch(L, 1, "black pair pass",
+                        [&] { return hmc::launch_pair_pass(L->d, 1, e, T, L->stream, &nb); });
+        if (st == HMC_OK)
+            st = launch(L, 2, "finalize kernel", [&] {
+                const int fl = hmc::kFinCounts | hmc::kFinObs | hmc::kFinTorque | (sample ? hmc::kFinSample : 0);
+                return hmc::launch_finalize(L->d, nr, nb, nb, fl, T, L->stream);
+            });
+        if (st != HMC_OK) return st;
+        L->m_valid = true;
+    }
+    return HMC_OK;
+}
+
+int hmc_observables(hmc_lattice* L, hmc_obs* out)
+{
+    if (!L || !out) return HMC_EINVAL;
+    int st = measure(L);
+    if (st != HMC_OK) return st;
+    DevState s;
+    hipError_t e = hipMemcpyAsync(&s, L->d.st, sizeof(s), hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "reading the device state", e);
+    memset(out, 0, sizeof(*out));
+    const double N = (double)L->d.N;
+    out->n = L->d.N;
+    out->sweeps_done = s.sweep;
+    out->samples = s.samples;
+    out->torque_samples = s.torque_samples;
+    out->accepted_last = s.accepted_last;
+    out->theta_deg = s.theta;
+    out->precision = L->d.precision;
+    for (int a = 0; a < 3; ++a) {
+        out->M[a] = s.M[a];
+        out->torque[a] = s.torque[a];
+    }
+    out->m = sqrt(s.M[0] * s.M[0] + s.M[1] * s.M[1] + s.M[2] * s.M[2]) / N;
+    out->E_exch = s.E_exch;
+    out->E_uni = s.E_uni;
+    out->E_cub = s.E_cub;
+    out->E_zee = s.E_zee;
+    out->E = s.E_exch + s.E_uni + s.E_cub + s.E_zee;
+    out->T_sample = s.T_sample;
+    if (s.samples > 0) {
+        const double ns = (double)s.samples;
+        for (int i = 0; i < 4; ++i) {
+            const double mu = s.sum[i] / ns;
+            out->mean_m[i] = s.shift[i] + mu;
+            out->var_m[i] = s.sum2[i] / ns - mu * mu;
+            out->chi[i] = s.T_sample > 0.0 ? N * out->var_m[i] / s.T_sample : 0.0;
+        }
+        const double mu = s.sum[4] / ns;
+        out->mean_E = s.shift[4] + mu;
+        out->var_E = s.sum2[4] / ns - mu * mu;
+        out->mean_Eanis = s.sum_eanis / ns;
+    }
+    if (s.torque_samples > 0)
+        for (int a = 0; a < 3; ++a) out->mean_torque[a] = s.sum_torque[a] / (double)s.torque_samples;
+    if (s.nonfinite) return fail(L, HMC_ENUMERIC, "a non-finite value appeared in the reductions");
+    return HMC_OK;
+}
+
+int hmc_reset_stats(hmc_lattice* L)
+{
+    if (!L) return HMC_EINVAL;
+    DevState s;
+    hipError_t e = hipMemcpyAsync(&s, L->d.st, sizeof(s), hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "reading the device state", e);
+    s.samples = 0;
+    s.torque_samples = 0;
+    for (int i = 0; i < 5; ++i) s.shift[i] = s.sum[i] = s.sum2[i] = 0.0;
+    s.sum_eanis = 0.0;
+    for (int a = 0; a < 3; ++a) s.sum_torque[a] = 0.0;
+    s.T_sample = 0.0;
+    L->init_state = s;
+    e = hipMemcpyAsync(L->d.st, &L->init_state, sizeof(s), hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "writing the device state", e);
+    return HMC_OK;
+}
+
+int hmc_copy_spins(hmc_lattice* L, double* host_xyz, int32_t to_host)
+{
+    if (!L || !host_xyz) return HMC_EINVAL;
+    const DevLattice& d = L->d;
+    const size_t rs = d.precision / 8;
+    const size_t bytes = (size_t)d.Nc * rs;
+    std::vector<char> buf;
+    try {
+        buf.resize(6 * bytes);
+    } catch (...) {
+        return fail(L, HMC_ENOMEM, "host staging buffer");
+    }
+    char* base = static_cast<char*>(d.spins);
+    auto get = [&](int c, int a, int64_t k) -> double {
+        const char* p = buf.data() + (size_t)(3 * c + a) * bytes;
+        return d.precision == 64 ? reinterpret_cast<const double*>(p)[k] : (double)reinterpret_cast<const float*>(p)[k];
+    };
+    auto put = [&](int c, int a, int64_t k, double v) {
+        char* p = buf.data() + (size_t)(3 * c + a) * bytes;
+        if (d.precision == 64) reinterpret_cast<double*>(p)[k] = v;
+        else reinterpret_cast<float*>(p)[k] = (float)v;
+    };
+    hipError_t e = hipSuccess;
+    if (to_host) {
+        for (int i = 0; i < 6 && e == hipSuccess; ++i)
+            e = hipMemcpyAsync(buf.data() + i * bytes, base + i * d.pitch, bytes, hipMemcpyDeviceToHost, L->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+        if (e != hipSuccess) return fail(L, HMC_EHIP, "copying spins to the host", e);
+    }
+    // site id i = 2k + p, colour c = (x + y + z) & 1
+    for (int64_t k = 0; k < d.Nc; ++k) {
+        const int64_t r = k / d.hx;
+        const int64_t y = r % d.ny, z = r / d.ny;
+        for (int c = 0; c < 2; ++c) {
+            const int64_t i = 2 * k + ((y + z + c) & 1);
+            for (int a = 0; a < 3; ++a) {
+                if (to_host) host_xyz[3 * i + a] = get(c, a, k);
+                else put(c, a, k, host_xyz[3 * i + a]);
+            }
+        }
+    }
+    if (!to_host) {
+        for (int i = 0; i < 6 && e == hipSuccess; ++i)
+            e = hipMemcpyAsync(base + i * d.pitch, buf.data() + i * bytes, bytes, hipMemcpyHostToDevice, L->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+        if (e != hipSuccess) return fail(L, HMC_EHIP, "copying spins to the device", e);
+        L->m_valid = false;
+    }
+    return HMC_OK;
+}
+
+size_t hmc_state_bytes(const hmc_lattice* L)
+{
+    if (!L) return 0;
+    return sizeof(StateHeader) + sizeof(DevState) + 6 * (size_t)L->d.Nc * (L->d.precision / 8);
+}
+
+static void fill_header(const hmc_lattice* L, StateHeader* h)
+{
+    memset(h, 0, sizeof(*h));
+    h->magic = kStateMagic;
+    h->precision = (uint32_t)L->p.precision;
+    h->nx = L->p.nx;
+    h->ny = L->p.ny;
+    h->nz = L->p.nz;
+    h->seed = L->p.seed;
+    h->instance = L->p.instance;
+    h->J = L->p.J;
+    h->Ku = L->p.Ku;
+    h->Kc = L->p.Kc;
+    for (int a = 0; a < 3; ++a) {
+        h->eu[a] = L->p.eu[a];
+        h->h[a] = L->p.h[a];
+    }
+}
+
+int hmc_get_state(hmc_lattice* L, void* host_buf, size_t bytes)
+{
+    if (!L || !host_buf) return HMC_EINVAL;
+    if (bytes < hmc_state_bytes(L)) return fail(L, HMC_ESTATE, "state buffer too small");
+    char* out = static_cast<char*>(host_buf);
+    StateHeader h;
+    fill_header(L, &h);
+    memcpy(out, &h, sizeof(h));
+    const size_t bytes_c = (size_t)L->d.Nc * (L->d.precision / 8);
+    char* base = static_cast<char*>(L->d.spins);
+    hipError_t e = hipMemcpyAsync(out + sizeof(h), L->d.st, sizeof(DevState), hipMemcpyDeviceToHost, L->stream);
+    for (int i = 0; i < 6 && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(out + sizeof(h) + sizeof(DevState) + i * bytes_c, base + i * L->d.pitch, bytes_c,
+                           hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "reading the state", e);
+    return HMC_OK;
+}
+
+int hmc_set_state(hmc_lattice* L, const void* host_buf, size_t bytes)
+{
+    if (!L || !host_buf) return HMC_EINVAL;
+    if (bytes < hmc_state_bytes(L)) return fail(L, HMC_ESTATE, "state buffer too small");
+    const char* in = static_cast<const char*>(host_buf);
+    StateHeader h, mine;
+    memcpy(&h, in, sizeof(h));
+    fill_header(L, &mine);
+    if (memcmp(&h, &mine, sizeof(h)) != 0) return fail(L, HMC_ESTATE, "state image belongs to another lattice");
+    const size_t bytes_c = (size_t)L->d.Nc * (L->d.precision / 8);
+    char* base = static_cast<char*>(L->d.spins);
+    memcpy(&L->init_state, in + sizeof(h), sizeof(DevState));
+    hipError_t e = hipMemcpyAsync(L->d.st, &L->init_state, sizeof(DevState), hipMemcpyHostToDevice, L->stream);
+    for (int i = 0; i < 6 && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(base + i * L->d.pitch, in + sizeof(h) + sizeof(DevState) + i * bytes_c, bytes_c,
+                           hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "writing the state", e);
+    L->m_valid = false;
+    return HMC_OK;
+}
+
+int hmc_set_launch(hmc_lattice* L, int32_t sites_per_thread, int32_t z_chunk)
+{
+    if (!L) return HMC_EINVAL;
+    if (sites_per_thread != 1 && sites_per_thread != 2 && sites_per_thread != 4)
+        return fail(L, HMC_EINVAL, "sites_per_thread must be 1, 2 or 4");
+    if (z_chunk < 1 || z_chunk > 1024) return fail(L, HMC_EINVAL, "z_chunk must be in [1, 1024]");
+    const size_t lds = 2 * 3 * (size_t)(hmc::kThreads * sites_per_thread + 2 * L->d.hx) * (L->d.precision / 8);
+    if (lds > 64 * 1024) return fail(L, HMC_EINVAL, "launch shape needs more than 64 KiB of LDS");
+    L->spt = sites_per_thread;
+    L->zc = z_chunk;
+    return HMC_OK;
+}
+
+int hmc_get_launch(const hmc_lattice* L, int32_t* sites_per_thread, int32_t* z_chunk)
+{
+    if (!L || !sites_per_thread || !z_chunk) return HMC_EINVAL;
+    *sites_per_thread = L->spt;
+    *z_chunk = L->zc;
+    return HMC_OK;
+}
+
+int hmc_set_timing(hmc_lattice* L, int32_t enable)
+{
+    if (!L) return HMC_EINVAL;
+    if (L->timing) {
+        int st = flush_timing(L);
+        if (st != HMC_OK) return st;
+    }
+    L->timing = enable != 0;
+    memset(&L->tot, 0, sizeof(L->tot));
+    // create the events up front so that a timed region does not pay for it
+    while (L->timing && L->ev.size() < 2 * kMaxEvents) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return fail(L, HMC_EHIP, "hipEventCreate", r);
+        L->ev.push_back(e);
+    }
+    return HMC_OK;
+}
+
+int hmc_read_timing(hmc_lattice* L, hmc_timing* out)
+{
+    if (!L || !out) return HMC_EINVAL;
+    int st = flush_timing(L);
+    if (st != HMC_OK) return st;
+    *out = L->tot;
+    return HMC_OK;
+}
+
+void hmc_destroy(hmc_lattice* L)
+{
+    if (!L) return;
+    (void)hipStreamSynchronize(L->stream);
+    for (hipEvent_t e : L->ev) (void)hipEventDestroy(e);
+    delete L;
+}
+
+const char* hmc_strerror(int status)
+{
+    switch (status) {
+    case HMC_OK: return "success";
+    case HMC_EINVAL: return "invalid argument";
+    case HMC_EDIM: return "invalid lattice dimensions";
+    case HMC_ENOMEM: return "workspace too small or misaligned";
+    case HMC_EHIP: return "HIP runtime error";
+    case HMC_ESTATE: return "state image does not match the lattice";
+    case HMC_ENUMERIC: return "non-finite value in the reductions";
+    default: return "unknown status";
+    }
+}
+
+const char* hmc_last_error(const hmc_lattice* L)
+{
+    return L ? L->err : "no lattice";
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// hmc_internal.h -- layout of the device workspace and the launchers that the
+// C interface (hmc_api.cpp) calls in the kernel translation unit
+// (hmc_kernels.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace hmc {
+
+constexpr int kThreads = 256;        // work-group size of every kernel
+constexpr int kMaxHalo = 4;          // halo slots per thread: nx <= 1024
+constexpr int kNumPart = 12;         // doubles per work-group partial
+constexpr size_t kAlign = 256;
+
+// Per-work-group partial sums written by the passes and reduced in a fixed
+// order by the finalize kernel.
+enum PartSlot {
+    kMx = 0, kMy, kMz,          // sum of S
+    kEexch, kEuni, kEcub, kEzee, // energy terms, each bond once
+    kTx, kTy, kTz,              // anisotropy torque
+};
+
+// Finalize flags.
+enum FinFlags {
+    kFinCounts = 1,      // reduce acceptance counts, adapt theta, advance the sweep counter
+    kFinObs = 2,         // reduce M and the energies into the state
+    kFinTorque = 4,      // also the torque
+    kFinSample = 8,      // add the reduced values to the accumulators
+};
+
+// Device-resident chain state (one per lattice, inside the workspace).
+struct DevState {
+    int32_t theta;            // cone angle, degrees
+    int32_t nonfinite;        // sticky: a reduction met a non-finite value
+    int64_t sweep;            // global sweep counter
+    int64_t accepted_last;
+    int64_t samples;
+    int64_t torque_samples;
+    int64_t reserved;
+    double M[3];
+    double E_exch, E_uni, E_cub, E_zee;
+    double torque[3];
+    double shift[5];          // first sample of (m_l, m_x, m_y, m_z, E/N)
+    double sum[5];            // sum of (x - shift)
+    double sum2[5];           // sum of (x - shift)^2
+    double sum_eanis;         // sum of (E_uni + E_cub)/N
+    double sum_torque[3];     // sum of torque/N over constrained samples
+    double T_sample;
+};
+
+// Everything a kernel launcher needs about one lattice.
+struct DevLattice {
+    int32_t precision;        // 32 or 64
+    int32_t nx, ny, nz;
+    int32_t hx;               // nx / 2
+    int32_t P;                // hx * ny: sites of one colour per plane
+    int64_t N;                // nx * ny * nz
+    int64_t Nc;               // N / 2: sites per colour
+    size_t pitch;             // bytes between the component arrays
+    void* spins;              // [colour][component][Nc] of float or double
+    DevState* st;
+    const void* c1tab;        // 181 reals: 1 - cos(theta) for theta in degrees
+    double* part;             // [max_blocks][kNumPart]
+    uint32_t* cnt;            // [2][max_blocks]
+    int64_t max_blocks;
+    double J, Ku, eu[3], Kc, h[3];
+    uint32_t key0, key1, instance;
+    int32_t init_mode;
+    double init_dir[3];
+};
+
+// Launchers (hmc_kernels.hip).  Each returns the HIP status of the launch;
+// *blocks receives the number of work-groups that wrote partials.
+hipError_t launch_init(const DevLattice& d, hipStream_t s);
+hipError_t launch_pass(const DevLattice& d, int colour, bool obs, int spt, int zc,
+                       double T, hipStream_t s, int64_t* blocks);
+hipError_t launch_pair_pass(const DevLattice& d, int colour, const double eC[3],
+                            double T, hipStream_t s, int64_t* blocks);
+hipError_t launch_measure(const DevLattice& d, hipStream_t s, int64_t* blocks);
+hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t black_blocks,
+                           int64_t part_blocks, int flags, double T, hipStream_t s);
+// Number of work-groups of the standard pass for a launch shape.
+int64_t pass_blocks(const DevLattice& d, int spt, int zc);
+// Largest partial count any launch shape can need.
+int64_t max_blocks_for(int32_t nx, int32_t ny, int32_t nz);
+
+}  // namespace hmc
