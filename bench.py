@@ -86,13 +86,19 @@ def time_leg(H, torch, shape, precision, T, steps, warmup, constrained=False, **
             done += c
 
     run(warmup)
-    torch.cuda.synchronize()
-    g.set_timing(True)
+    # timed region: K steps, nothing else on the stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the same workload again with a HIP event pair recorded around every
+    # kernel on the lattice's stream (the events stretch the gaps between
+    # kernels, so they stay out of the region above)
+    ksteps = max(steps // 2, 1)
+    g.set_timing(True)
+    torch.cuda.synchronize()
+    run(ksteps)
     tm = g.read_timing()
     g.set_timing(False)
     ob = g.observables()
@@ -103,6 +109,7 @@ def time_leg(H, torch, shape, precision, T, steps, warmup, constrained=False, **
         "ms_per_step": 1e3 * secs / steps,
         "kernels_ms": {k: (v["total_ms"] / v["count"] if v["count"] else None) for k, v in tm.items()},
         "kernel_counts": {k: v["count"] for k, v in tm.items()},
+        "kernel_timing_steps": ksteps,
         "theta_deg": ob["theta_deg"],
         "mean_m": ob["mean_m"][0],
         "launch": g.get_launch(),
@@ -135,6 +142,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference leg")
     ap.add_argument("--main-only", action="store_true", help="only the 256^3 FP32 leg")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="run a few 256^3 FP32 sweeps and nothing else (for counter runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy a 1 GiB buffer a few times (scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sharded "
@@ -146,6 +157,22 @@ def main():
     import paper_2103_03517_amd as H
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     H.lib()
+    if args.copy_calibration:
+        # a plain device-to-device copy of 2^30 bytes: reads and writes 1 GiB
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 1073741824 bytes")
+        return
+    if args.profile_pass:
+        g = H.Lattice(256, 256, 256, precision=32, J=1.0, Ku=0.005, eu=(0, 0, 1), seed=7,
+                      init="random")
+        g.sweep(1.0, 10, sample=True)
+        torch.cuda.synchronize()
+        log("profile-pass: 10 sampled 256^3 FP32 sweeps (20 colour passes)")
+        return
     dev = torch.cuda.get_device_properties(0)
     log(f"device: {dev.name}, {dev.multi_processor_count} CUs")
 
@@ -217,6 +244,9 @@ def main():
     for k, v in extra.items():
         line[k] = {"value": v["value"], "unit": "spin updates/s", "ms_per_step": v["ms_per_step"],
                    "kernels_ms": v["kernels_ms"]}
+    line["kernel_timing"] = ("per-kernel averages from HIP events recorded by the library on the "
+                             f"lattice's stream over a second region of {main_leg['kernel_timing_steps']} "
+                             "steps of the same workload")
     if cpu is not None:
         line["speedup_vs_cpu_baseline"] = main_leg["value"] / cpu["value"]
     print(json.dumps(line), flush=True)

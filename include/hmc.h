@@ -61,7 +61,8 @@ typedef struct hmc_lattice hmc_lattice;
 typedef struct {
     int32_t  nx, ny, nz;    /* each even and >= 2 (the red/black colouring of a
                                periodic axis needs an even length, Sec. 2);
-                               nx*ny*nz < 2^32 */
+                               nx <= 1024; nx*ny*nz < 2^32 and
+                               nx*ny*nz*precision/16 < 2^32 bytes */
     int32_t  precision;     /* 32: FP32 spins and energy changes, FP64 sums;
                                64: FP64 throughout */
     double   J;             /* exchange (energy unit) */
@@ -104,9 +105,10 @@ typedef struct {
 } hmc_obs;
 
 /* Per-kernel timing collected with HIP events on the handle's stream while
- * timing is enabled.  Kinds: 0 = standard colour pass, 1 = constrained
- * pair pass, 2 = per-sweep finalize (reductions, cone angle),
- * 3 = other (initialisation, measurement). */
+ * timing is enabled.  Kinds: 0 = standard colour pass, 1 = constrained pair
+ * pass, 2 = reductions (the per-sweep finalize: cone angle, counters,
+ * accumulators; and the measurement of the current spins),
+ * 3 = initialisation. */
 typedef struct {
     int64_t count[4];
     double  total_ms[4];
@@ -156,8 +158,9 @@ int hmc_reset_stats(hmc_lattice* L);
 
 /* Copies the spins between the device and host_xyz, an array of 3*N
  * doubles in AoS order S[3*i + a] with site id i = x + nx*(y + ny*z).
- * to_host != 0: device -> host; else host -> device (FP32 lattices round
- * to nearest).  Synchronises. */
+ * to_host != 0: device -> host; else host -> device, each vector divided by
+ * its length (zero or non-finite vectors are stored as given; FP32 lattices
+ * round to nearest).  Synchronises. */
 int hmc_copy_spins(hmc_lattice* L, double* host_xyz, int32_t to_host);
 
 /* Checkpoint: hmc_state_bytes() gives the size of a state image (spins,

@@ -52,7 +52,7 @@ class Timing(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
 
 
-TIMING_KINDS = ("pass", "pair_pass", "finalize", "other")
+TIMING_KINDS = ("pass", "pair_pass", "reduce", "init")
 
 # every function declared in include/hmc.h
 SYMBOLS = ("hmc_workspace_bytes", "hmc_init_lattice", "hmc_sweep", "hmc_constrained_sweep",

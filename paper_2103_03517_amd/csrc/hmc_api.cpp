@@ -49,6 +49,11 @@ int validate(const hmc_params* p, char* msg, size_t n)
         snprintf(msg, n, "precision must be 32 or 64 (got %d)", p->precision);
         return HMC_EINVAL;
     }
+    // each component array is addressed by 32-bit byte offsets
+    if (N / 2 * (uint64_t)(p->precision / 8) > 0xFFFFFFFFull) {
+        snprintf(msg, n, "lattice too large: one component array must stay below 4 GiB");
+        return HMC_EDIM;
+    }
     if (!isfinite(p->J) || !isfinite(p->Ku) || !isfinite(p->Kc) || !finite3(p->eu) || !finite3(p->h)) {
         snprintf(msg, n, "model constants must be finite");
         return HMC_EINVAL;
@@ -175,11 +180,11 @@ int launch(hmc_lattice* L, int kind, const char* what, F f)
 int measure(hmc_lattice* L)
 {
     int64_t nb = 0;
-    int st = launch(L, 3, "measure kernel", [&] { return hmc::launch_measure(L->d, L->stream, &nb); });
-    if (st != HMC_OK) return st;
-    st = launch(L, 3, "finalize kernel", [&] {
-        return hmc::launch_finalize(L->d, 0, 0, nb, hmc::kFinObs | hmc::kFinTorque, 0.0, L->stream);
-    });
+    int st = launch(L, 2, "measure kernel", [&] { return hmc::launch_measure(L->d, L->stream, &nb); });
+    if (st == HMC_OK)
+        st = launch(L, 2, "finalize kernel", [&] {
+            return hmc::launch_finalize(L->d, 0, nb, hmc::kFinObs | hmc::kFinTorque, 0.0, L->stream);
+        });
     if (st == HMC_OK) L->m_valid = true;
     return st;
 }
@@ -256,8 +261,8 @@ int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes, void* h
         L->c1f[th] = (float)L->c1d[th];
     }
     // default launch shape: 512 in-plane sites per work-group, 16 planes,
-    // narrowed to 256 sites when the LDS window would exceed 64 KiB
-    if (2 * 3 * (size_t)(hmc::kThreads * L->spt + 2 * d.hx) * (p->precision / 8) > 64 * 1024) L->spt = 1;
+    // narrowed to 256 sites when the LDS window would exceed its budget
+    if (hmc::pass_lds_bytes(p->precision, d.hx, L->spt) > hmc::kMaxLds) L->spt = 1;
     memset(&L->init_state, 0, sizeof(L->init_state));
     L->init_state.theta = p->theta0_deg;
 
@@ -293,8 +298,8 @@ int hmc_sweep(hmc_lattice* L, double T, int32_t n_sweeps, int32_t sample)
             });
         if (st == HMC_OK)
             st = launch(L, 2, "finalize kernel", [&] {
-                const int fl = hmc::kFinCounts | (obs ? (hmc::kFinObs | hmc::kFinSample) : 0);
-                return hmc::launch_finalize(L->d, nr, nb, obs ? nb : 0, fl, T, L->stream);
+                const int fin = hmc::kFinCounts | (obs ? (hmc::kFinObs | hmc::kFinSample) : 0);
+                return hmc::launch_finalize(L->d, nr, nb, fin, T, L->stream);
             });
         if (st != HMC_OK) return st;
         L->m_valid = obs;
@@ -316,14 +321,15 @@ int hmc_constrained_sweep(hmc_lattice* L, double T, const double eC[3], int32_t 
     }
     for (int32_t it = 0; it < n_sweeps; ++it) {
         int64_t nr = 0, nb = 0;
-        int st = launch(L, 1, "red pair pass", [&] { return hmc::launch_pair_pass(L->d, 0, e, T, L->stream, &nr); });
+        int st = launch(L, 1, "red pair pass",
+                        [&] { return hmc::launch_pair_pass(L->d, 0, e, T, L->stream, &nr); });
         if (st == HMC_OK)
             st = launch(L, 1, "black pair pass",
                         [&] { return hmc::launch_pair_pass(L->d, 1, e, T, L->stream, &nb); });
         if (st == HMC_OK)
             st = launch(L, 2, "finalize kernel", [&] {
-                const int fl = hmc::kFinCounts | hmc::kFinObs | hmc::kFinTorque | (sample ? hmc::kFinSample : 0);
-                return hmc::launch_finalize(L->d, nr, nb, nb, fl, T, L->stream);
+                const int fin = hmc::kFinCounts | hmc::kFinObs | hmc::kFinTorque | (sample ? hmc::kFinSample : 0);
+                return hmc::launch_finalize(L->d, nr, nb, fin, T, L->stream);
             });
         if (st != HMC_OK) return st;
         L->m_valid = true;
@@ -434,9 +440,15 @@ int hmc_copy_spins(hmc_lattice* L, double* host_xyz, int32_t to_host)
         const int64_t y = r % d.ny, z = r / d.ny;
         for (int c = 0; c < 2; ++c) {
             const int64_t i = 2 * k + ((y + z + c) & 1);
-            for (int a = 0; a < 3; ++a) {
-                if (to_host) host_xyz[3 * i + a] = get(c, a, k);
-                else put(c, a, k, host_xyz[3 * i + a]);
+            if (to_host) {
+                for (int a = 0; a < 3; ++a) host_xyz[3 * i + a] = get(c, a, k);
+            } else {
+                // directions are normalised on the way in; zero or non-finite
+                // vectors are stored as given
+                const double* v = host_xyz + 3 * i;
+                const double n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+                const double inv = (n2 > 0.0 && isfinite(n2)) ? 1.0 / sqrt(n2) : 1.0;
+                for (int a = 0; a < 3; ++a) put(c, a, k, v[a] * inv);
             }
         }
     }
@@ -522,8 +534,8 @@ int hmc_set_launch(hmc_lattice* L, int32_t sites_per_thread, int32_t z_chunk)
     if (sites_per_thread != 1 && sites_per_thread != 2 && sites_per_thread != 4)
         return fail(L, HMC_EINVAL, "sites_per_thread must be 1, 2 or 4");
     if (z_chunk < 1 || z_chunk > 1024) return fail(L, HMC_EINVAL, "z_chunk must be in [1, 1024]");
-    const size_t lds = 2 * 3 * (size_t)(hmc::kThreads * sites_per_thread + 2 * L->d.hx) * (L->d.precision / 8);
-    if (lds > 64 * 1024) return fail(L, HMC_EINVAL, "launch shape needs more than 64 KiB of LDS");
+    if (hmc::pass_lds_bytes(L->d.precision, L->d.hx, sites_per_thread) > hmc::kMaxLds)
+        return fail(L, HMC_EINVAL, "launch shape needs more than 64 KiB of LDS");
     L->spt = sites_per_thread;
     L->zc = z_chunk;
     return HMC_OK;

@@ -19,6 +19,12 @@ namespace hmc {
 // ---------------------------------------------------------------------------
 struct Rand4 { uint32_t r0, r1, r2, r3; };
 
+// a ^ b ^ c in one gfx950 V_BITOP3 (truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Rand4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1)
 {
@@ -26,8 +32,8 @@ __device__ __forceinline__ Rand4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
         const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -72,6 +78,25 @@ __device__ __forceinline__ uint32_t shuffle_index(uint32_t x, uint32_t n, uint32
     return x;
 }
 
+// Inverse of shuffle_index: the rounds undone in reverse order, walking with
+// the inverse bijection until the preimage falls inside [0, n).
+__device__ __forceinline__ uint32_t unshuffle_index(uint32_t y, uint32_t n, uint32_t half,
+                                                    uint32_t mask, const Rand4 key)
+{
+    const uint32_t k[4] = {key.r0, key.r1, key.r2, key.r3};
+    do {
+        uint32_t lo = y & mask, hi = y >> half;
+#pragma unroll
+        for (int round = 3; round >= 0; --round) {
+            const uint32_t plo = hi;
+            hi = lo ^ (mix32(plo ^ k[round]) & mask);
+            lo = plo;
+        }
+        y = (hi << half) | lo;
+    } while (y >= n);
+    return y;
+}
+
 // ---------------------------------------------------------------------------
 // Precision-specific primitives.  FP32 uses the hardware transcendentals
 // (v_sin/v_cos take revolutions, v_exp is 2^x, v_rsq, v_rcp, v_sqrt);
@@ -80,10 +105,13 @@ __device__ __forceinline__ uint32_t shuffle_index(uint32_t x, uint32_t n, uint32
 template <typename R> struct Prim;
 
 template <> struct Prim<float> {
-    // ((r >> 9) + 1/2) 2^-23: 24 significant bits, exact in FP32, in (0, 1).
+    // ((r >> 9) + 1/2) 2^-23, in (0, 1): the top 23 bits become the mantissa
+    // of a float in [1, 2) (one V_ALIGNBIT shifts them under the exponent
+    // 0x7F), from which 1 - 2^-24 is subtracted exactly (both operands within
+    // a factor of 2).
     static __device__ __forceinline__ float u01(uint32_t r)
     {
-        return __builtin_fmaf((float)(r >> 9), 0x1p-23f, 0x1p-24f);
+        return __builtin_bit_cast(float, __builtin_amdgcn_alignbit(0x7Fu, r, 9u)) - 0x1.fffffep-1f;
     }
     static __device__ __forceinline__ void sincos_turns(float u, float* s, float* c)
     {
@@ -107,10 +135,10 @@ template <> struct Prim<double> {
     {
         return __builtin_fma((double)r, 0x1p-32, 0x1p-33);
     }
+    // sin and cos of 2 pi u (sincospi needs no argument reduction by pi).
     static __device__ __forceinline__ void sincos_turns(double u, double* s, double* c)
     {
-        const double phi = 6.283185307179586 * u;
-        sincos(phi, s, c);
+        sincospi(2.0 * u, s, c);
     }
     static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
     static __device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
@@ -154,7 +182,9 @@ __device__ __forceinline__ V3<R> cone_move(const V3<R>& s, R u0, R u1, R c1)
     v.x = cosa * s.x + sina * (cp * b1.x + sp * b2.x);
     v.y = cosa * s.y + sina * (cp * b1.y + sp * b2.y);
     v.z = cosa * s.z + sina * (cp * b1.z + sp * b2.z);
-    const R inv = P::rsqrt_(dot(v, v));
+    // |v|^2 = 1 + e with e of the order of the rounding error; one Newton step
+    // for 1/sqrt(1 + e) is exact to O(e^2)
+    const R inv = R(1.5) - R(0.5) * dot(v, v);
     return V3<R>{v.x * inv, v.y * inv, v.z * inv};
 }
 
@@ -165,18 +195,36 @@ template <typename R> struct Model {
     V3<R> h;   // field
 };
 
+// One-site terms of Eq. 2 kept for the observables: projection on the
+// uniaxial axis and the cubic function, of the old and the proposed spin.
+template <typename R> struct SiteTerms { R se, te, cs, ct; };
+
 // Energy change of one site (Eq. 2) when s becomes t, with the local field
 // hl = J * (sum of the six neighbours) + h.
 template <typename R>
-__device__ __forceinline__ R delta_e(const Model<R>& m, const V3<R>& s, const V3<R>& t, const V3<R>& hl)
+__device__ __forceinline__ R delta_e(const Model<R>& m, const V3<R>& s, const V3<R>& t, const V3<R>& hl,
+                                     SiteTerms<R>& k)
 {
     R dE = -((t.x - s.x) * hl.x + (t.y - s.y) * hl.y + (t.z - s.z) * hl.z);
+    k = SiteTerms<R>{R(0), R(0), R(0), R(0)};
     if (m.Ku != R(0)) {
-        const R se = dot(s, m.e), te = dot(t, m.e);
-        dE -= m.Ku * (te - se) * (te + se);
+        k.se = dot(s, m.e);
+        k.te = dot(t, m.e);
+        dE -= m.Ku * (k.te - k.se) * (k.te + k.se);
     }
-    if (m.Kc != R(0)) dE += m.Kc * (cubic_f(t) - cubic_f(s));
+    if (m.Kc != R(0)) {
+        k.cs = cubic_f(s);
+        k.ct = cubic_f(t);
+        dE += m.Kc * (k.ct - k.cs);
+    }
     return dE;
+}
+
+template <typename R>
+__device__ __forceinline__ R delta_e(const Model<R>& m, const V3<R>& s, const V3<R>& t, const V3<R>& hl)
+{
+    SiteTerms<R> k;
+    return delta_e(m, s, t, hl, k);
 }
 
 // Site contributions to the observables, accumulated in FP64.

@@ -13,6 +13,7 @@ constexpr int kThreads = 256;        // work-group size of every kernel
 constexpr int kMaxHalo = 4;          // halo slots per thread: nx <= 1024
 constexpr int kNumPart = 12;         // doubles per work-group partial
 constexpr size_t kAlign = 256;
+constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS budget of one work-group
 
 // Per-work-group partial sums written by the passes and reduced in a fixed
 // order by the finalize kernel.
@@ -22,10 +23,10 @@ enum PartSlot {
     kTx, kTy, kTz,              // anisotropy torque
 };
 
-// Finalize flags.
+// What the finalize kernel folds into the chain state.
 enum FinFlags {
-    kFinCounts = 1,      // reduce acceptance counts, adapt theta, advance the sweep counter
-    kFinObs = 2,         // reduce M and the energies into the state
+    kFinCounts = 1,      // acceptance counts: adapt theta, advance the sweep counter
+    kFinObs = 2,         // M and the energies
     kFinTorque = 4,      // also the torque
     kFinSample = 8,      // add the reduced values to the accumulators
 };
@@ -38,7 +39,6 @@ struct DevState {
     int64_t accepted_last;
     int64_t samples;
     int64_t torque_samples;
-    int64_t reserved;
     double M[3];
     double E_exch, E_uni, E_cub, E_zee;
     double torque[3];
@@ -72,18 +72,22 @@ struct DevLattice {
 };
 
 // Launchers (hmc_kernels.hip).  Each returns the HIP status of the launch;
-// *blocks receives the number of work-groups that wrote partials.
+// *blocks receives the number of work-groups that wrote results.
 hipError_t launch_init(const DevLattice& d, hipStream_t s);
-hipError_t launch_pass(const DevLattice& d, int colour, bool obs, int spt, int zc,
-                       double T, hipStream_t s, int64_t* blocks);
-hipError_t launch_pair_pass(const DevLattice& d, int colour, const double eC[3],
-                            double T, hipStream_t s, int64_t* blocks);
+hipError_t launch_pass(const DevLattice& d, int colour, bool obs, int spt, int zc, double T, hipStream_t s,
+                       int64_t* blocks);
+hipError_t launch_pair_pass(const DevLattice& d, int colour, const double eC[3], double T, hipStream_t s,
+                            int64_t* blocks);
 hipError_t launch_measure(const DevLattice& d, hipStream_t s, int64_t* blocks);
-hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t black_blocks,
-                           int64_t part_blocks, int flags, double T, hipStream_t s);
+// Reduces the results of the colour-1 launch (black_blocks work-groups; for
+// the counts also the red_blocks of the colour-0 launch) into the state.
+hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t black_blocks, int fin, double T,
+                           hipStream_t s);
 // Number of work-groups of the standard pass for a launch shape.
 int64_t pass_blocks(const DevLattice& d, int spt, int zc);
-// Largest partial count any launch shape can need.
+// Dynamic LDS bytes of the standard pass for a launch shape.
+size_t pass_lds_bytes(int precision, int hx, int spt);
+// Largest partial count any launch can need.
 int64_t max_blocks_for(int32_t nx, int32_t ny, int32_t nz);
 
 }  // namespace hmc

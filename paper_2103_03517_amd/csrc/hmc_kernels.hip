@@ -8,6 +8,10 @@
 // Every kernel reads one colour as neighbours and writes only the other, so a
 // colour pass has no read/write overlap (Sec. 2: the two sets do not
 // interact in Eq. 2).
+//
+// Global memory is accessed through buffer resources: the per-plane offset
+// travels in a scalar register, so the per-column offsets are computed once,
+// and out-of-range accesses are dropped by the hardware.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -17,10 +21,13 @@
 
 namespace hmc {
 
+constexpr int32_t kBufferConfig = 0x00020000;   // raw buffer, gfx9-family data format
+
 template <typename R>
 struct KArgs {
     R* s[2][3];
     uint32_t hx, ny, nz, P, Nc;
+    uint32_t arr_bytes;  // bytes of one component array (range of the buffer resources)
     Model<R> m;
     uint32_t key0, key1, inst;
     DevState* st;
@@ -42,6 +49,7 @@ static KArgs<R> make_args(const DevLattice& d)
     a.nz = (uint32_t)d.nz;
     a.P = (uint32_t)d.P;
     a.Nc = (uint32_t)d.Nc;
+    a.arr_bytes = (uint32_t)((uint64_t)d.Nc * sizeof(R));
     a.m.J = (R)d.J;
     a.m.Ku = (R)d.Ku;
     a.m.Kc = (R)d.Kc;
@@ -58,6 +66,103 @@ static KArgs<R> make_args(const DevLattice& d)
     return a;
 }
 
+// ---------------------------------------------------------------------------
+// Buffer-resource access to the six component arrays.
+// ---------------------------------------------------------------------------
+template <typename R> struct Gm;
+
+template <> struct Gm<float> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    }
+};
+
+template <> struct Gm<double> {
+    static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double v)
+    {
+        using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
+    }
+};
+
+template <typename R>
+struct Arrays {
+    __amdgpu_buffer_rsrc_t r[2][3];
+    __device__ __forceinline__ explicit Arrays(const KArgs<R>& a)
+    {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                r[c][k] = __builtin_amdgcn_make_buffer_rsrc(a.s[c][k], 0, (int)a.arr_bytes, kBufferConfig);
+    }
+    // spin of colour c at byte offset voff + soff
+    __device__ __forceinline__ V3<R> get(int c, uint32_t voff, uint32_t soff) const
+    {
+        return V3<R>{Gm<R>::ld(r[c][0], voff, soff), Gm<R>::ld(r[c][1], voff, soff), Gm<R>::ld(r[c][2], voff, soff)};
+    }
+    __device__ __forceinline__ void put(int c, uint32_t voff, uint32_t soff, const V3<R>& v) const
+    {
+        Gm<R>::st(r[c][0], voff, soff, v.x);
+        Gm<R>::st(r[c][1], voff, soff, v.y);
+        Gm<R>::st(r[c][2], voff, soff, v.z);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// LDS plane of the other colour: float4 entries for FP32 (one 16-byte access
+// per neighbour), three component planes for FP64.
+// ---------------------------------------------------------------------------
+template <typename R> struct LdsPlane;
+
+template <> struct LdsPlane<float> {
+    static constexpr size_t bytes_per_entry = 16;
+    static __device__ __forceinline__ void put(unsigned char* p, uint32_t W, uint32_t e, const V3<float>& v)
+    {
+        (void)W;
+        reinterpret_cast<float4*>(p)[e] = make_float4(v.x, v.y, v.z, 0.0f);
+    }
+    static __device__ __forceinline__ V3<float> get(const unsigned char* p, uint32_t W, uint32_t e)
+    {
+        (void)W;
+        const float4 q = reinterpret_cast<const float4*>(p)[e];
+        return V3<float>{q.x, q.y, q.z};
+    }
+};
+
+template <> struct LdsPlane<double> {
+    static constexpr size_t bytes_per_entry = 24;
+    static __device__ __forceinline__ void put(unsigned char* p, uint32_t W, uint32_t e, const V3<double>& v)
+    {
+        double* d = reinterpret_cast<double*>(p);
+        d[e] = v.x;
+        d[W + e] = v.y;
+        d[2 * W + e] = v.z;
+    }
+    static __device__ __forceinline__ V3<double> get(const unsigned char* p, uint32_t W, uint32_t e)
+    {
+        const double* d = reinterpret_cast<const double*>(p);
+        return V3<double>{d[e], d[W + e], d[2 * W + e]};
+    }
+};
+
+size_t pass_lds_bytes(int precision, int hx, int spt)
+{
+    const size_t W = (size_t)kThreads * spt + 2 * (size_t)hx;
+    const size_t e = precision == 32 ? LdsPlane<float>::bytes_per_entry : LdsPlane<double>::bytes_per_entry;
+    const size_t b = 2 * W * e;
+    return b < 1024 ? 1024 : b;
+}
+
 // Work-groups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Renumber them so that XCD x receives one contiguous range of logical
 // tiles: neighbouring tiles, whose halos overlap, then share an L2.
@@ -68,8 +173,12 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nblk)
     return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
 }
 
-// Work-group sum in a fixed order (butterfly within each wave, then waves in
-// order), so results do not depend on scheduling.
+// ---------------------------------------------------------------------------
+// Fixed-order reductions.  Within a wave a butterfly, across the four waves
+// of a work-group in wave order, across work-groups by the finalize kernel,
+// each thread taking work-groups t, t+256, ... in order.  The results
+// therefore do not depend on scheduling.
+// ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
@@ -78,42 +187,139 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// Sums NV values over the work-group; the totals land in scratch[0..NV).
 template <int NV>
-__device__ __forceinline__ void block_sum_write(double (&v)[NV], double* scratch, double* out)
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    __syncthreads();
     if (lane == 0)
 #pragma unroll
-        for (int i = 0; i < NV; ++i) scratch[wave * NV + i] = v[i];
+        for (int i = 0; i < NV; ++i) scratch[NV + wave * NV + i] = v[i];
     __syncthreads();
     if (threadIdx.x < NV) {
         double s = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) s += scratch[w * NV + threadIdx.x];
-        out[threadIdx.x] = s;
+        for (int w = 0; w < kThreads / 64; ++w) s += scratch[NV + w * NV + threadIdx.x];
+        scratch[threadIdx.x] = s;
     }
-}
-
-__device__ __forceinline__ void block_count_write(uint32_t v, uint32_t* scratch, uint32_t* out)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    v = wave_sum(v);
-    if (lane == 0) scratch[wave] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int w = 0; w < kThreads / 64; ++w) s += scratch[w];
-        *out = s;
+}
+
+// The end of a producing launch: work-group b writes its acceptance count
+// and (OBS) its partial sums.  They are reduced by finalize_kernel, launched
+// next on the same stream (the kernel boundary makes them visible).
+template <typename R, bool OBS>
+__device__ __forceinline__ void block_end(const KArgs<R>& a, int colour, uint32_t b, uint32_t nacc, const Acc& acc,
+                                          double* scratch)
+{
+    if (OBS) {
+        double v[kNumPart] = {acc.M[0], acc.M[1], acc.M[2], acc.ex, acc.eu, acc.ec, acc.ez,
+                              acc.tq[0], acc.tq[1], acc.tq[2], (double)nacc, 0.0};
+        block_sum<kNumPart>(v, scratch);
+        if (threadIdx.x < kNumPart) a.part[(size_t)b * kNumPart + threadIdx.x] = scratch[threadIdx.x];
+        if (threadIdx.x == 0) a.cnt[(size_t)colour * a.cnt_stride + b] = (uint32_t)scratch[10];
+    } else {
+        uint32_t c = wave_sum(nacc);
+        __syncthreads();
+        uint32_t* s32 = reinterpret_cast<uint32_t*>(scratch);
+        if ((threadIdx.x & 63) == 0) s32[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < kThreads / 64; ++w) tot += s32[w];
+            a.cnt[(size_t)colour * a.cnt_stride + b] = tot;
+        }
     }
 }
 
-template <typename R>
-__device__ __forceinline__ void write_partials(const Acc& acc, double* part, uint32_t b, double* scratch)
+// ---------------------------------------------------------------------------
+// Per-sweep finalize (one work-group): the fixed-order reduction of the
+// work-group results of the colour-1 (and, for the counts, colour-0) launch,
+// then Table A1's cone-angle rule (one degree up when accepted/N > 1/2, else
+// down, within [1, 180]), the sweep counter and on sampled sweeps the
+// shifted FP64 accumulators of Eq. 6.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void finalize_kernel(DevState* st, const double* part, const uint32_t* cnt,
+                                                            uint32_t cnt_stride, uint32_t nred, uint32_t nblack,
+                                                            int fin, double T, double N)
 {
-    double v[kNumPart] = {acc.M[0], acc.M[1], acc.M[2], acc.ex, acc.eu, acc.ec, acc.ez,
-                          acc.tq[0], acc.tq[1], acc.tq[2], 0.0, 0.0};
-    block_sum_write<kNumPart>(v, scratch, part + (size_t)b * kNumPart);
+    __shared__ double scratch[5 * (kNumPart + 1)];
+    const uint32_t t = threadIdx.x;
+    double v[kNumPart + 1];
+#pragma unroll
+    for (int i = 0; i <= kNumPart; ++i) v[i] = 0.0;
+    if (fin & kFinCounts) {
+        unsigned long long c = 0;
+        for (uint32_t i = t; i < nred; i += kThreads) c += cnt[i];
+        for (uint32_t i = t; i < nblack; i += kThreads) c += cnt[cnt_stride + i];
+        v[kNumPart] = (double)c;
+    }
+    if (fin & kFinObs) {
+        // each thread takes whole 96-byte records: six independent 16-byte loads
+        for (uint32_t i = t; i < nblack; i += kThreads) {
+            const double2* p = reinterpret_cast<const double2*>(part + (size_t)i * kNumPart);
+#pragma unroll
+            for (int k = 0; k < kNumPart / 2; ++k) {
+                const double2 q = p[k];
+                v[2 * k] += q.x;
+                v[2 * k + 1] += q.y;
+            }
+        }
+    }
+    block_sum<kNumPart + 1>(v, scratch);
+    if (t != 0) return;
+    const double* tot = scratch;
+    if (fin & kFinCounts) {
+        const long long accepted = (long long)tot[kNumPart];
+        st->accepted_last = accepted;
+        if (2.0 * (double)accepted > N) {
+            if (st->theta < 180) st->theta += 1;
+        } else {
+            if (st->theta > 1) st->theta -= 1;
+        }
+        st->sweep += 1;
+    }
+    if (fin & kFinObs) {
+        bool finite = true;
+        for (int i = 0; i < 10; ++i) finite = finite && isfinite(tot[i]);
+        if (!finite) st->nonfinite = 1;
+        st->M[0] = tot[kMx];
+        st->M[1] = tot[kMy];
+        st->M[2] = tot[kMz];
+        st->E_exch = tot[kEexch];
+        st->E_uni = tot[kEuni];
+        st->E_cub = tot[kEcub];
+        st->E_zee = tot[kEzee];
+        if (fin & kFinTorque) {
+            st->torque[0] = tot[kTx];
+            st->torque[1] = tot[kTy];
+            st->torque[2] = tot[kTz];
+        }
+        if (fin & kFinSample) {
+            double x[5];
+            x[1] = tot[kMx] / N;
+            x[2] = tot[kMy] / N;
+            x[3] = tot[kMz] / N;
+            x[0] = sqrt(x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+            x[4] = (tot[kEexch] + tot[kEuni] + tot[kEcub] + tot[kEzee]) / N;
+            if (st->samples == 0)
+                for (int i = 0; i < 5; ++i) st->shift[i] = x[i];
+            for (int i = 0; i < 5; ++i) {
+                const double d = x[i] - st->shift[i];
+                st->sum[i] += d;
+                st->sum2[i] += d * d;
+            }
+            st->sum_eanis += (tot[kEuni] + tot[kEcub]) / N;
+            if (fin & kFinTorque) {
+                for (int i = 0; i < 3; ++i) st->sum_torque[i] += tot[kTx + i] / N;
+                st->torque_samples += 1;
+            }
+            st->samples += 1;
+            st->T_sample = T;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -144,6 +350,39 @@ __global__ __launch_bounds__(kThreads) void init_kernel(const KArgs<R> a, int mo
 }
 
 // ---------------------------------------------------------------------------
+// The Metropolis update of one site (Table A1, Eq. 1, Eq. 2): cone proposal,
+// energy change in the local field, acceptance P < exp(-dE/T).  Returns the
+// final spin; OBS adds the site and its red x-partner to the observables.
+// ---------------------------------------------------------------------------
+template <typename R, bool OBS>
+__device__ __forceinline__ V3<R> update_site(const Model<R>& m, const V3<R>& s, const V3<R>& nb,
+                                             const V3<R>& partner, const Rand4& rn, R c1, R scale,
+                                             uint32_t& nacc, Acc& acc)
+{
+    const V3<R> hl{m.J * nb.x + m.h.x, m.J * nb.y + m.h.y, m.J * nb.z + m.h.z};
+    const V3<R> tr = cone_move(s, Prim<R>::u01(rn.r0), Prim<R>::u01(rn.r1), c1);
+    SiteTerms<R> k;
+    const R dE = delta_e(m, s, tr, hl, k);
+    const bool ok = Prim<R>::u01(rn.r2) < Prim<R>::boltzmann(dE, scale);
+    const V3<R> f = ok ? tr : s;
+    nacc += ok ? 1u : 0u;
+    if (OBS) {
+        const V3<R> fp{f.x + partner.x, f.y + partner.y, f.z + partner.z};
+        acc.M[0] += (double)fp.x;
+        acc.M[1] += (double)fp.y;
+        acc.M[2] += (double)fp.z;
+        acc.ex += (double)(-m.J * dot(f, nb));
+        if (m.Ku != R(0)) {
+            const R sf = ok ? k.te : k.se, sp = dot(partner, m.e);
+            acc.eu += (double)(-m.Ku * (sf * sf + sp * sp));
+        }
+        if (m.Kc != R(0)) acc.ec += (double)(m.Kc * ((ok ? k.ct : k.cs) + cubic_f(partner)));
+        acc.ez += (double)(-dot(m.h, fp));
+    }
+    return f;
+}
+
+// ---------------------------------------------------------------------------
 // Standard colour pass (Table A1, MonteCarlo_Red(Black)ParallelPass).
 //
 // A work-group owns Q = 256*SPT consecutive in-plane colour indices and
@@ -152,182 +391,174 @@ __global__ __launch_bounds__(kThreads) void init_kernel(const KArgs<R> a, int mo
 // z+1 values at the owned columns stay in registers.  Each plane of each
 // colour is therefore fetched once per pass (plus a halo of 2*hx entries per
 // plane), and the loads for plane z+1/z+2 are issued before plane z is
-// computed.  OBS (black pass only) fuses the observables: the black site after
-// its update plus its red x-partner (same colour index), and the exchange of
-// the black site with its six final red neighbours, so every site and every
-// bond is counted once.
+// computed.  The march is unrolled by four so that the four register planes
+// rotate by renaming.  OBS (black pass only) fuses the observables: the black
+// site after its update plus its red x-partner (same colour index), and the
+// exchange of the black site with its six final red neighbours, so every
+// site and every bond is counted once.
 // ---------------------------------------------------------------------------
-template <typename R, int C, bool OBS, int SPT>
-__global__ __launch_bounds__(kThreads) void pass_kernel(const KArgs<R> a, const uint32_t zc,
-                                                        const uint32_t nqb, const uint32_t nblk,
-                                                        const R scale)
+template <typename R, int SPT, int HALO>
+struct PassCtx {
+    uint32_t hx, P, nz, W, z0, zn;
+    uint32_t voff[SPT];          // byte offset of each owned column in a plane
+    uint32_t w[SPT];             // its LDS entry
+    uint32_t wd[2][SPT];         // LDS entry of its second x-neighbour, by z parity
+    uint32_t par[SPT];           // x parity of the column at z = z0
+    bool act[SPT];
+    uint32_t hvoff[HALO], hw[HALO];
+    bool hact[HALO];
+    unsigned char* lds[2];
+    R c1, scale;
+    uint32_t sweep;
+};
+
+template <typename R, int C, bool OBS, int SPT, int HALO, int K>
+__device__ __forceinline__ void pass_step(const KArgs<R>& a, const Arrays<R>& g, const PassCtx<R, SPT, HALO>& x,
+                                          uint32_t zi, V3<R> (&om)[SPT], V3<R> (&o0)[SPT], V3<R> (&op)[SPT],
+                                          V3<R> (&opp)[SPT], V3<R> (&sc)[SPT], V3<R> (&sn)[SPT],
+                                          V3<R> (&hp)[HALO], V3<R> (&hpp)[HALO], uint32_t& nacc, Acc& acc)
+{
+    constexpr int O = 1 - C;
+    constexpr int B = K & 1;
+    const uint32_t z = x.z0 + zi;
+    const bool more = zi + 1 < x.zn;
+    auto plane_off = [&](uint32_t zz) -> uint32_t {
+        return x.P * (uint32_t)sizeof(R) * (zz >= x.nz ? zz - x.nz : zz);
+    };
+    if (more) {
+        const uint32_t fpp = plane_off(z + 2), fn = plane_off(z + 1);
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            opp[j] = g.get(O, x.voff[j], fpp);
+            sn[j] = g.get(C, x.voff[j], fn);
+        }
+#pragma unroll
+        for (int i = 0; i < HALO; ++i)
+            if (x.hact[i]) hpp[i] = g.get(O, x.hvoff[i], fpp);
+    }
+    const unsigned char* L = x.lds[B];
+    const uint32_t fz = plane_off(z);
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        if (!x.act[j]) continue;
+        const uint32_t p = x.par[j] ^ (uint32_t)B;
+        const V3<R> xd = LdsPlane<R>::get(L, x.W, x.wd[B][j]);
+        const V3<R> ym = LdsPlane<R>::get(L, x.W, x.w[j] - x.hx);
+        const V3<R> yp = LdsPlane<R>::get(L, x.W, x.w[j] + x.hx);
+        const V3<R> xm = p ? o0[j] : xd;
+        const V3<R> xp = p ? xd : o0[j];
+        const V3<R> nb{((((xm.x + xp.x) + ym.x) + yp.x) + om[j].x) + op[j].x,
+                       ((((xm.y + xp.y) + ym.y) + yp.y) + om[j].y) + op[j].y,
+                       ((((xm.z + xp.z) + ym.z) + yp.z) + om[j].z) + op[j].z};
+        const uint32_t k = x.voff[j] / (uint32_t)sizeof(R) + x.P * (z >= x.nz ? z - x.nz : z);
+        const Rand4 rn = philox(x.sweep, 2u * k + p, (uint32_t)C, a.inst, a.key0, a.key1);
+        const V3<R> f = update_site<R, OBS>(a.m, sc[j], nb, o0[j], rn, x.c1, x.scale, nacc, acc);
+        g.put(C, x.voff[j], fz, f);
+    }
+    if (more) {
+        unsigned char* Ln = x.lds[B ^ 1];
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) LdsPlane<R>::put(Ln, x.W, x.w[j], op[j]);
+#pragma unroll
+        for (int i = 0; i < HALO; ++i)
+            if (x.hact[i]) LdsPlane<R>::put(Ln, x.W, x.hw[i], hp[i]);
+    }
+    __syncthreads();
+}
+
+template <typename R, int C, bool OBS, int SPT, int HALO>
+__global__ __launch_bounds__(kThreads) void pass_kernel(const KArgs<R> a, const uint32_t zc, const uint32_t nqb,
+                                                        const uint32_t nblk, const R scale)
 {
     constexpr int O = 1 - C;
     constexpr uint32_t Q = kThreads * SPT;
     extern __shared__ __align__(16) unsigned char smem[];
-    R* lds = reinterpret_cast<R*>(smem);
 
-    const uint32_t hx = a.hx, P = a.P, nz = a.nz;
-    const uint32_t W = Q + 2u * hx;
+    const Arrays<R> g(a);
+    PassCtx<R, SPT, HALO> x;
+    x.hx = a.hx;
+    x.P = a.P;
+    x.nz = a.nz;
+    x.W = Q + 2u * a.hx;
     const uint32_t t = threadIdx.x;
     const uint32_t b = xcd_remap(blockIdx.x, nblk);
     const uint32_t qb = b % nqb, zb = b / nqb;
     const uint32_t base = qb * Q;
-    const uint32_t z0 = zb * zc;
-    const uint32_t zn = min(zc, nz - z0);
+    x.z0 = zb * zc;
+    x.zn = min(zc, a.nz - x.z0);
+    x.lds[0] = smem;
+    x.lds[1] = smem + (size_t)x.W * LdsPlane<R>::bytes_per_entry;
+    x.c1 = a.c1tab[a.st->theta];
+    x.sweep = (uint32_t)a.st->sweep;
+    x.scale = scale;
 
-    const int theta = a.st->theta;
-    const uint32_t sweep = (uint32_t)a.st->sweep;
-    const R c1 = a.c1tab[theta];
-    const Model<R> m = a.m;
-
-    uint32_t qm[SPT], kx[SPT], yy[SPT];
-    bool act[SPT];
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
         const uint32_t q = base + t + kThreads * j;
-        act[j] = q < P;
-        qm[j] = act[j] ? q : q % P;
-        kx[j] = qm[j] % hx;
-        yy[j] = qm[j] / hx;
-    }
-    // halo slots of the LDS window: window index and in-plane index
-    const uint32_t nh = 2u * hx;
-    uint32_t hw[kMaxHalo], hg[kMaxHalo];
+        x.act[j] = q < a.P;
+        const uint32_t qm = x.act[j] ? q : q % a.P;
+        const uint32_t kx = qm % a.hx, yy = qm / a.hx;
+        x.voff[j] = qm * (uint32_t)sizeof(R);
+        x.w[j] = a.hx + t + kThreads * j;
+        x.par[j] = (yy + x.z0 + (uint32_t)C) & 1u;
+        // window entry of the x-neighbour that is not the same-index partner:
+        // x+1 (wrapping inside the row) when the site's x is odd, else x-1
 #pragma unroll
-    for (int i = 0; i < kMaxHalo; ++i) {
+        for (int bpar = 0; bpar < 2; ++bpar) {
+            const uint32_t p = x.par[j] ^ (uint32_t)bpar;
+            const uint32_t w = x.w[j];
+            x.wd[bpar][j] = p ? (kx == a.hx - 1 ? w + 1 - a.hx : w + 1) : (kx == 0 ? w + a.hx - 1 : w - 1);
+        }
+    }
+    const uint32_t nh = 2u * a.hx;
+#pragma unroll
+    for (int i = 0; i < HALO; ++i) {
         const uint32_t slot = t + kThreads * i;
-        hw[i] = slot < hx ? slot : slot + Q;
-        hg[i] = (base + hw[i] + P - hx) % P;
+        x.hact[i] = slot < nh;
+        x.hw[i] = slot < a.hx ? slot : slot + Q;
+        x.hvoff[i] = ((base + x.hw[i] + a.P - a.hx) % a.P) * (uint32_t)sizeof(R);
     }
-    auto plane = [&](int zz) -> uint32_t {
-        const int w = zz < 0 ? zz + (int)nz : (zz >= (int)nz ? zz - (int)nz : zz);
-        return P * (uint32_t)w;
-    };
 
-    R om[SPT][3], o0[SPT][3], op[SPT][3], opp[SPT][3];
-    R sc[SPT][3], sn[SPT][3];
-    R hp[kMaxHalo][3], hpp[kMaxHalo][3];
-
-    // prologue: planes z0-1, z0, z0+1 of the other colour, window of z0 in LDS
+    V3<R> rA[SPT], rB[SPT], rC[SPT], rD[SPT], s0[SPT], s1[SPT], h0[HALO], h1[HALO];
     {
-        const uint32_t fm = plane((int)z0 - 1), f0 = plane((int)z0), fp = plane((int)z0 + 1);
+        auto plane_off = [&](int zz) -> uint32_t {
+            const int w = zz < 0 ? zz + (int)a.nz : (zz >= (int)a.nz ? zz - (int)a.nz : zz);
+            return a.P * (uint32_t)sizeof(R) * (uint32_t)w;
+        };
+        const uint32_t fm = plane_off((int)x.z0 - 1), f0 = plane_off((int)x.z0), fp = plane_off((int)x.z0 + 1);
 #pragma unroll
-        for (int j = 0; j < SPT; ++j)
+        for (int j = 0; j < SPT; ++j) {
+            rA[j] = g.get(O, x.voff[j], fm);
+            rB[j] = g.get(O, x.voff[j], f0);
+            rC[j] = g.get(O, x.voff[j], fp);
+            s0[j] = g.get(C, x.voff[j], f0);
+        }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                om[j][c] = a.s[O][c][qm[j] + fm];
-                o0[j][c] = a.s[O][c][qm[j] + f0];
-                op[j][c] = a.s[O][c][qm[j] + fp];
-                sc[j][c] = a.s[C][c][qm[j] + f0];
+        for (int i = 0; i < HALO; ++i)
+            if (x.hact[i]) {
+                LdsPlane<R>::put(x.lds[0], x.W, x.hw[i], g.get(O, x.hvoff[i], f0));
+                h0[i] = g.get(O, x.hvoff[i], fp);
             }
 #pragma unroll
-        for (int i = 0; i < kMaxHalo; ++i)
-            if (t + kThreads * i < nh)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    lds[c * W + hw[i]] = a.s[O][c][hg[i] + f0];
-                    hp[i][c] = a.s[O][c][hg[i] + fp];
-                }
-#pragma unroll
-        for (int j = 0; j < SPT; ++j)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) lds[c * W + hx + t + kThreads * j] = o0[j][c];
+        for (int j = 0; j < SPT; ++j) LdsPlane<R>::put(x.lds[0], x.W, x.w[j], rB[j]);
     }
     __syncthreads();
 
     uint32_t nacc = 0;
     Acc acc;
-
-    for (uint32_t zi = 0; zi < zn; ++zi) {
-        const uint32_t z = z0 + zi;
-        const bool more = zi + 1 < zn;
-        if (more) {
-            const uint32_t fpp = plane((int)z + 2), fn = plane((int)z + 1);
-#pragma unroll
-            for (int j = 0; j < SPT; ++j)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    opp[j][c] = a.s[O][c][qm[j] + fpp];
-                    sn[j][c] = a.s[C][c][qm[j] + fn];
-                }
-#pragma unroll
-            for (int i = 0; i < kMaxHalo; ++i)
-                if (t + kThreads * i < nh)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) hpp[i][c] = a.s[O][c][hg[i] + fpp];
-        }
-
-        const R* Lw = lds + (zi & 1u) * 3u * W;
-        const uint32_t fz = P * z;
-#pragma unroll
-        for (int j = 0; j < SPT; ++j) {
-            if (!act[j]) continue;
-            const uint32_t w = hx + t + kThreads * j;
-            const uint32_t p = (yy[j] + z + (uint32_t)C) & 1u;
-            // window index of the x-neighbour that is not the same-k partner
-            const uint32_t wd = p ? (kx[j] == hx - 1 ? w + 1 - hx : w + 1)
-                                  : (kx[j] == 0 ? w + hx - 1 : w - 1);
-            R nb[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const R xd = Lw[c * W + wd];
-                const R xm = p ? o0[j][c] : xd;
-                const R xp = p ? xd : o0[j][c];
-                nb[c] = ((((xm + xp) + Lw[c * W + w - hx]) + Lw[c * W + w + hx]) + om[j][c]) + op[j][c];
-            }
-            const V3<R> hl{m.J * nb[0] + m.h.x, m.J * nb[1] + m.h.y, m.J * nb[2] + m.h.z};
-            const V3<R> s{sc[j][0], sc[j][1], sc[j][2]};
-            const uint32_t k = qm[j] + fz;
-            const Rand4 rn = philox(sweep, 2u * k + p, (uint32_t)C, a.inst, a.key0, a.key1);
-            const V3<R> tr = cone_move(s, Prim<R>::u01(rn.r0), Prim<R>::u01(rn.r1), c1);
-            const R dE = delta_e(m, s, tr, hl);
-            const bool ok = Prim<R>::u01(rn.r2) < Prim<R>::boltzmann(dE, scale);
-            const V3<R> f = ok ? tr : s;
-            a.s[C][0][k] = f.x;
-            a.s[C][1][k] = f.y;
-            a.s[C][2][k] = f.z;
-            nacc += ok ? 1u : 0u;
-            if (OBS) {
-                const V3<R> partner{o0[j][0], o0[j][1], o0[j][2]};
-                acc.ex += (double)(-m.J * (f.x * nb[0] + f.y * nb[1] + f.z * nb[2]));
-                add_site<R, false>(acc, m, f);
-                add_site<R, false>(acc, m, partner);
-            }
-        }
-
-        if (more) {
-            R* Ln = lds + ((zi + 1u) & 1u) * 3u * W;
-#pragma unroll
-            for (int j = 0; j < SPT; ++j)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) Ln[c * W + hx + t + kThreads * j] = op[j][c];
-#pragma unroll
-            for (int i = 0; i < kMaxHalo; ++i)
-                if (t + kThreads * i < nh)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) Ln[c * W + hw[i]] = hp[i][c];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < SPT; ++j)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                om[j][c] = o0[j][c];
-                o0[j][c] = op[j][c];
-                op[j][c] = opp[j][c];
-                sc[j][c] = sn[j][c];
-            }
-#pragma unroll
-        for (int i = 0; i < kMaxHalo; ++i)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) hp[i][c] = hpp[i][c];
+    uint32_t zi = 0;
+    for (; zi + 4 <= x.zn; zi += 4) {
+        pass_step<R, C, OBS, SPT, HALO, 0>(a, g, x, zi + 0, rA, rB, rC, rD, s0, s1, h0, h1, nacc, acc);
+        pass_step<R, C, OBS, SPT, HALO, 1>(a, g, x, zi + 1, rB, rC, rD, rA, s1, s0, h1, h0, nacc, acc);
+        pass_step<R, C, OBS, SPT, HALO, 2>(a, g, x, zi + 2, rC, rD, rA, rB, s0, s1, h0, h1, nacc, acc);
+        pass_step<R, C, OBS, SPT, HALO, 3>(a, g, x, zi + 3, rD, rA, rB, rC, s1, s0, h1, h0, nacc, acc);
     }
+    if (zi < x.zn) pass_step<R, C, OBS, SPT, HALO, 0>(a, g, x, zi + 0, rA, rB, rC, rD, s0, s1, h0, h1, nacc, acc);
+    if (zi + 1 < x.zn) pass_step<R, C, OBS, SPT, HALO, 1>(a, g, x, zi + 1, rB, rC, rD, rA, s1, s0, h1, h0, nacc, acc);
+    if (zi + 2 < x.zn) pass_step<R, C, OBS, SPT, HALO, 2>(a, g, x, zi + 2, rC, rD, rA, rB, s0, s1, h0, h1, nacc, acc);
 
-    // LDS is free after the last barrier of the loop
-    double* scratch = reinterpret_cast<double*>(smem);
-    block_count_write(nacc, reinterpret_cast<uint32_t*>(scratch + 64), a.cnt + (size_t)C * a.cnt_stride + b);
-    if (OBS) write_partials<R>(acc, a.part, b, scratch);
+    // LDS is free after the last barrier of the march
+    block_end<R, OBS>(a, C, b, nacc, acc, reinterpret_cast<double*>(smem));
 }
 
 // ---------------------------------------------------------------------------
@@ -336,10 +567,11 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(const KArgs<R> a, const 
 // x-partner with the same index.  Used by the gather kernels.
 // ---------------------------------------------------------------------------
 template <typename R, int C>
-__device__ __forceinline__ void gather_neighbours(const KArgs<R>& a, uint32_t k, V3<R>& nb, V3<R>& partner,
-                                                  uint32_t& site)
+__device__ __forceinline__ void gather_neighbours(const KArgs<R>& a, const Arrays<R>& g, uint32_t k, V3<R>& nb,
+                                                  V3<R>& partner, uint32_t& site)
 {
     constexpr int O = 1 - C;
+    constexpr uint32_t rs = sizeof(R);
     const uint32_t hx = a.hx, ny = a.ny, nz = a.nz, P = a.P;
     const uint32_t kx = k % hx, r = k / hx;
     const uint32_t y = r % ny, z = r / ny;
@@ -353,37 +585,39 @@ __device__ __forceinline__ void gather_neighbours(const KArgs<R>& a, uint32_t k,
     const uint32_t inpl = kx + hx * y;
     const uint32_t zm = inpl + P * (z == 0 ? nz - 1 : z - 1);
     const uint32_t zp = inpl + P * (z == nz - 1 ? 0 : z + 1);
-    R v[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const R* o = a.s[O][c];
-        const R same = o[k], xd = o[d];
-        const R xm = p ? same : xd;
-        const R xp = p ? xd : same;
-        v[c] = ((((xm + xp) + o[ym]) + o[yp]) + o[zm]) + o[zp];
-        (&partner.x)[c] = same;
-    }
-    nb = V3<R>{v[0], v[1], v[2]};
+    const V3<R> same = g.get(O, k * rs, 0), xd = g.get(O, d * rs, 0);
+    const V3<R> vym = g.get(O, ym * rs, 0), vyp = g.get(O, yp * rs, 0);
+    const V3<R> vzm = g.get(O, zm * rs, 0), vzp = g.get(O, zp * rs, 0);
+    const V3<R> xm = p ? same : xd;
+    const V3<R> xp = p ? xd : same;
+    nb = V3<R>{((((xm.x + xp.x) + vym.x) + vyp.x) + vzm.x) + vzp.x,
+               ((((xm.y + xp.y) + vym.y) + vyp.y) + vzm.y) + vzp.y,
+               ((((xm.z + xp.z) + vym.z) + vyp.z) + vzm.z) + vzp.z};
+    partner = same;
 }
 
 // ---------------------------------------------------------------------------
-// Constrained pair pass (Table A2, ConstrainedMonteCarlo_ParallelPass), one
-// thread per pair of colour C.  The shuffled order pi of the colour indices
-// is a keyed bijection evaluated inline (nothing is stored); pair k is
-// (pi(2k), pi(2k+1)).  M_L is the moment along eC at the start of the sweep
-// (one value for both colours, as in the paper).  OBS (black pass) fuses the
-// observables over the two black sites and their red x-partners; because pi
-// is a bijection every site is covered once.
+// Constrained pair pass (Table A2, ConstrainedMonteCarlo_ParallelPass) of
+// colour C.  The shuffled order pi of the colour indices is a keyed
+// bijection evaluated inline (nothing is stored); pair k is
+// (pi(2k), pi(2k+1)).  One thread per colour index a: the thread whose a is
+// the first spin of its pair (pi^-1(a) even) runs the pair move, so the first
+// spin and its neighbours are read coalesced and only the partner is a
+// random gather.  M_L is the moment along eC at the start of the sweep (one
+// value for both colours, as in the paper).  OBS (black pass) fuses the
+// observables over the two black sites and their red x-partners; since pi is
+// a bijection every site is covered once.
 // ---------------------------------------------------------------------------
 template <typename R, int C, bool OBS>
 __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, const V3<R> ec, const uint32_t half,
-                                                        const uint32_t mask, const uint32_t npairs, const R scale)
+                                                        const uint32_t mask, const R scale)
 {
-    __shared__ double scratch[kNumPart * (kThreads / 64) + 8];
-    const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
-    const int theta = a.st->theta;
+    __shared__ double scratch[8 * kNumPart];
+    constexpr uint32_t rs = sizeof(R);
+    const Arrays<R> g(a);
+    const uint32_t ia = blockIdx.x * kThreads + threadIdx.x;
     const uint32_t sweep = (uint32_t)a.st->sweep;
-    const R c1 = a.c1tab[theta];
+    const R c1 = a.c1tab[a.st->theta];
     const Model<R> m = a.m;
     const double* M = a.st->M;
     const double ML = M[0] * (double)ec.x + M[1] * (double)ec.y + M[2] * (double)ec.z;
@@ -392,15 +626,16 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, const 
 
     uint32_t nacc = 0;
     Acc acc;
-    if (k < npairs) {
-        const uint32_t ia = shuffle_index(2u * k, a.Nc, half, mask, key);
-        const uint32_t ja = shuffle_index(2u * k + 1u, a.Nc, half, mask, key);
+    const uint32_t pos = ia < a.Nc ? unshuffle_index(ia, a.Nc, half, mask, key) : 1u;
+    if ((pos & 1u) == 0u) {
+        const uint32_t k = pos >> 1;
+        const uint32_t ja = shuffle_index(pos + 1u, a.Nc, half, mask, key);
         V3<R> nbi, nbj, pti, ptj;
         uint32_t site_i, site_j;
-        gather_neighbours<R, C>(a, ia, nbi, pti, site_i);
-        gather_neighbours<R, C>(a, ja, nbj, ptj, site_j);
-        const V3<R> si{a.s[C][0][ia], a.s[C][1][ia], a.s[C][2][ia]};
-        const V3<R> sj{a.s[C][0][ja], a.s[C][1][ja], a.s[C][2][ja]};
+        gather_neighbours<R, C>(a, g, ia, nbi, pti, site_i);
+        gather_neighbours<R, C>(a, g, ja, nbj, ptj, site_j);
+        const V3<R> si = g.get(C, ia * rs, 0);
+        const V3<R> sj = g.get(C, ja * rs, 0);
         const Rand4 rn = philox(sweep, k, 2u + (uint32_t)C, a.inst, a.key0, a.key1);
         const V3<R> ti = cone_move(si, Prim<R>::u01(rn.r0), Prim<R>::u01(rn.r1), c1);
 
@@ -415,18 +650,18 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, const 
         const R pj_new = (pj_old >= R(0) ? R(1) : R(-1)) * Prim<R>::sqrt_(ok ? q : R(1));
         const V3<R> tj{pj.x + pj_new * ec.x, pj.y + pj_new * ec.y, pj.z + pj_new * ec.z};
         // (M_L'/M_L)^2 with M_L' = |M_L| + change along eC
-        const R x = ((pi_new + pj_new) - pi_old - pj_old) * invML;
-        ok = ok && (R(1) + x > R(0)) && (ML != 0.0);
+        const R xr = ((pi_new + pj_new) - pi_old - pj_old) * invML;
+        ok = ok && (R(1) + xr > R(0)) && (ML != 0.0);
         const V3<R> hi{m.J * nbi.x + m.h.x, m.J * nbi.y + m.h.y, m.J * nbi.z + m.h.z};
         const V3<R> hj{m.J * nbj.x + m.h.x, m.J * nbj.y + m.h.y, m.J * nbj.z + m.h.z};
         const R dE = delta_e(m, si, ti, hi) + delta_e(m, sj, tj, hj);
-        const R ratio = (R(1) + x) * (R(1) + x) * fabs(pj_old / pj_new);
+        const R ratio = (R(1) + xr) * (R(1) + xr) * fabs(pj_old / pj_new);
         ok = ok && (Prim<R>::u01(rn.r2) < ratio * Prim<R>::boltzmann(dE, scale));
         const V3<R> fi = ok ? ti : si;
         const V3<R> fj = ok ? tj : sj;
         if (ok) {
-            a.s[C][0][ia] = ti.x; a.s[C][1][ia] = ti.y; a.s[C][2][ia] = ti.z;
-            a.s[C][0][ja] = tj.x; a.s[C][1][ja] = tj.y; a.s[C][2][ja] = tj.z;
+            g.put(C, ia * rs, 0, ti);
+            g.put(C, ja * rs, 0, tj);
             nacc = 2;
         }
         if (OBS) {
@@ -437,125 +672,31 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, const 
             add_site<R, true>(acc, m, ptj);
         }
     }
-    block_count_write(nacc, reinterpret_cast<uint32_t*>(scratch + kNumPart * (kThreads / 64)),
-                      a.cnt + (size_t)C * a.cnt_stride + blockIdx.x);
-    if (OBS) write_partials<R>(acc, a.part, blockIdx.x, scratch);
+    block_end<R, OBS>(a, C, blockIdx.x, nacc, acc, scratch);
 }
 
 // ---------------------------------------------------------------------------
 // Measurement of the current spins: one thread per colour index k covers the
 // black site k (with its six red neighbours: every bond once) and the red
-// site k.
+// site k; the last work-group stores M, the energies and the torque.
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(kThreads) void measure_kernel(const KArgs<R> a)
 {
-    __shared__ double scratch[kNumPart * (kThreads / 64) + 8];
+    __shared__ double scratch[8 * kNumPart];
+    const Arrays<R> g(a);
     const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
     Acc acc;
     if (k < a.Nc) {
         V3<R> nb, red;
         uint32_t site;
-        gather_neighbours<R, 1>(a, k, nb, red, site);
-        const V3<R> blk{a.s[1][0][k], a.s[1][1][k], a.s[1][2][k]};
+        gather_neighbours<R, 1>(a, g, k, nb, red, site);
+        const V3<R> blk = g.get(1, k * (uint32_t)sizeof(R), 0);
         acc.ex += (double)(-a.m.J * dot(blk, nb));
         add_site<R, true>(acc, a.m, blk);
         add_site<R, true>(acc, a.m, red);
     }
-    write_partials<R>(acc, a.part, blockIdx.x, scratch);
-}
-
-// ---------------------------------------------------------------------------
-// Per-sweep finalize (one work-group): fixed-order reduction of the
-// work-group partials, the adaptive cone angle of Table A1 (one degree up
-// when accepted/N > 1/2, else down, within [1, 180]), the sweep counter,
-// and on sampled sweeps the shifted FP64 accumulators of Eq. 6.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void finalize_kernel(DevState* st, const double* part, const uint32_t* cnt,
-                                                            uint32_t cnt_stride, uint32_t nred, uint32_t nblack,
-                                                            uint32_t npart, int flags, double T, double N)
-{
-    __shared__ double red_d[kThreads];
-    __shared__ unsigned long long red_i[kThreads];
-    __shared__ double tot[kNumPart];
-    const uint32_t t = threadIdx.x;
-
-    unsigned long long c = 0;
-    if (flags & kFinCounts) {
-        for (uint32_t i = t; i < nred; i += kThreads) c += cnt[i];
-        for (uint32_t i = t; i < nblack; i += kThreads) c += cnt[cnt_stride + i];
-    }
-    red_i[t] = c;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if (t < (uint32_t)s) red_i[t] += red_i[t + s];
-        __syncthreads();
-    }
-    if (flags & kFinObs) {
-        for (int slot = 0; slot < kNumPart; ++slot) {
-            double v = 0.0;
-            for (uint32_t i = t; i < npart; i += kThreads) v += part[(size_t)i * kNumPart + slot];
-            red_d[t] = v;
-            __syncthreads();
-            for (int s = kThreads / 2; s > 0; s >>= 1) {
-                if (t < (uint32_t)s) red_d[t] += red_d[t + s];
-                __syncthreads();
-            }
-            if (t == 0) tot[slot] = red_d[0];
-            __syncthreads();
-        }
-    }
-    if (t != 0) return;
-
-    if (flags & kFinCounts) {
-        const long long accepted = (long long)red_i[0];
-        st->accepted_last = accepted;
-        if (2.0 * (double)accepted > N) {
-            if (st->theta < 180) st->theta += 1;
-        } else {
-            if (st->theta > 1) st->theta -= 1;
-        }
-        st->sweep += 1;
-    }
-    if (flags & kFinObs) {
-        bool finite = true;
-        for (int i = 0; i < 10; ++i) finite = finite && isfinite(tot[i]);
-        if (!finite) st->nonfinite = 1;
-        st->M[0] = tot[kMx];
-        st->M[1] = tot[kMy];
-        st->M[2] = tot[kMz];
-        st->E_exch = tot[kEexch];
-        st->E_uni = tot[kEuni];
-        st->E_cub = tot[kEcub];
-        st->E_zee = tot[kEzee];
-        if (flags & kFinTorque) {
-            st->torque[0] = tot[kTx];
-            st->torque[1] = tot[kTy];
-            st->torque[2] = tot[kTz];
-        }
-        if (flags & kFinSample) {
-            double x[5];
-            x[1] = tot[kMx] / N;
-            x[2] = tot[kMy] / N;
-            x[3] = tot[kMz] / N;
-            x[0] = sqrt(x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
-            x[4] = (tot[kEexch] + tot[kEuni] + tot[kEcub] + tot[kEzee]) / N;
-            if (st->samples == 0)
-                for (int i = 0; i < 5; ++i) st->shift[i] = x[i];
-            for (int i = 0; i < 5; ++i) {
-                const double d = x[i] - st->shift[i];
-                st->sum[i] += d;
-                st->sum2[i] += d * d;
-            }
-            st->sum_eanis += (tot[kEuni] + tot[kEcub]) / N;
-            if (flags & kFinTorque) {
-                for (int i = 0; i < 3; ++i) st->sum_torque[i] += tot[kTx + i] / N;
-                st->torque_samples += 1;
-            }
-            st->samples += 1;
-            st->T_sample = T;
-        }
-    }
+    block_end<R, true>(a, 1, blockIdx.x, 0u, acc, scratch);
 }
 
 // ---------------------------------------------------------------------------
@@ -566,7 +707,10 @@ static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b -
 int64_t max_blocks_for(int32_t nx, int32_t ny, int32_t nz)
 {
     const uint64_t P = (uint64_t)(nx / 2) * (uint64_t)ny;
-    return (int64_t)cdiv(P, kThreads) * (int64_t)nz;
+    const uint64_t Nc = P * (uint64_t)nz;
+    const int64_t pass = (int64_t)cdiv(P, kThreads) * (int64_t)nz;
+    const int64_t gather = (int64_t)cdiv(Nc, kThreads);
+    return pass > gather ? pass : gather;
 }
 
 int64_t pass_blocks(const DevLattice& d, int spt, int zc)
@@ -588,32 +732,42 @@ hipError_t launch_init(const DevLattice& d, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename R, int C, bool OBS, int SPT>
-static void pass_go(const DevLattice& d, int zc, double T, hipStream_t s)
+template <typename R, int C, bool OBS, int SPT, int HALO>
+static void pass_go(const KArgs<R>& a, const DevLattice& d, int zc, double T, hipStream_t s)
 {
-    const auto a = make_args<R>(d);
     const uint32_t nqb = cdiv((uint64_t)d.P, (uint64_t)kThreads * SPT);
     const uint32_t nzb = cdiv((uint64_t)d.nz, (uint64_t)zc);
     const uint32_t nblk = nqb * nzb;
-    const size_t lds = 2 * 3 * (size_t)(kThreads * SPT + 2 * d.hx) * sizeof(R);
-    pass_kernel<R, C, OBS, SPT><<<nblk, kThreads, lds < 1024 ? 1024 : lds, s>>>(a, (uint32_t)zc, nqb, nblk,
-                                                                                 Prim<R>::scale_for(T));
+    pass_kernel<R, C, OBS, SPT, HALO><<<nblk, kThreads, pass_lds_bytes(d.precision, d.hx, SPT), s>>>(
+        a, (uint32_t)zc, nqb, nblk, Prim<R>::scale_for(T));
+}
+
+template <typename R, int SPT, int HALO>
+static void pass_dispatch_c(const KArgs<R>& a, const DevLattice& d, int colour, bool obs, int zc, double T,
+                            hipStream_t s)
+{
+    if (colour == 0) pass_go<R, 0, false, SPT, HALO>(a, d, zc, T, s);
+    else if (obs) pass_go<R, 1, true, SPT, HALO>(a, d, zc, T, s);
+    else pass_go<R, 1, false, SPT, HALO>(a, d, zc, T, s);
 }
 
 template <typename R, int SPT>
-static void pass_dispatch_c(const DevLattice& d, int colour, bool obs, int zc, double T, hipStream_t s)
+static void pass_dispatch_h(const KArgs<R>& a, const DevLattice& d, int colour, bool obs, int zc, double T,
+                            hipStream_t s)
 {
-    if (colour == 0) pass_go<R, 0, false, SPT>(d, zc, T, s);
-    else if (obs) pass_go<R, 1, true, SPT>(d, zc, T, s);
-    else pass_go<R, 1, false, SPT>(d, zc, T, s);
+    const int halo = (2 * d.hx + kThreads - 1) / kThreads;
+    if (halo <= 1) pass_dispatch_c<R, SPT, 1>(a, d, colour, obs, zc, T, s);
+    else if (halo == 2) pass_dispatch_c<R, SPT, 2>(a, d, colour, obs, zc, T, s);
+    else pass_dispatch_c<R, SPT, 4>(a, d, colour, obs, zc, T, s);
 }
 
 template <typename R>
 static void pass_dispatch(const DevLattice& d, int colour, bool obs, int spt, int zc, double T, hipStream_t s)
 {
-    if (spt == 1) pass_dispatch_c<R, 1>(d, colour, obs, zc, T, s);
-    else if (spt == 2) pass_dispatch_c<R, 2>(d, colour, obs, zc, T, s);
-    else pass_dispatch_c<R, 4>(d, colour, obs, zc, T, s);
+    const auto a = make_args<R>(d);
+    if (spt == 1) pass_dispatch_h<R, 1>(a, d, colour, obs, zc, T, s);
+    else if (spt == 2) pass_dispatch_h<R, 2>(a, d, colour, obs, zc, T, s);
+    else pass_dispatch_h<R, 4>(a, d, colour, obs, zc, T, s);
 }
 
 hipError_t launch_pass(const DevLattice& d, int colour, bool obs, int spt, int zc, double T, hipStream_t s,
@@ -634,12 +788,11 @@ static void pair_go(const DevLattice& d, int colour, const double eC[3], double 
     while (bits < 32 && (1ull << bits) < n) bits += 2;
     const uint32_t half = bits / 2;
     const uint32_t mask = half >= 32 ? 0xFFFFFFFFu : ((1u << half) - 1u);
-    const uint32_t npairs = n / 2;
     const V3<R> ec{(R)eC[0], (R)eC[1], (R)eC[2]};
-    const uint32_t grid = cdiv(npairs, kThreads);
+    const uint32_t grid = cdiv(n, kThreads);
     const R scale = Prim<R>::scale_for(T);
-    if (colour == 0) pair_kernel<R, 0, false><<<grid, kThreads, 0, s>>>(a, ec, half, mask, npairs, scale);
-    else pair_kernel<R, 1, true><<<grid, kThreads, 0, s>>>(a, ec, half, mask, npairs, scale);
+    if (colour == 0) pair_kernel<R, 0, false><<<grid, kThreads, 0, s>>>(a, ec, half, mask, scale);
+    else pair_kernel<R, 1, true><<<grid, kThreads, 0, s>>>(a, ec, half, mask, scale);
 }
 
 hipError_t launch_pair_pass(const DevLattice& d, int colour, const double eC[3], double T, hipStream_t s,
@@ -647,7 +800,7 @@ hipError_t launch_pair_pass(const DevLattice& d, int colour, const double eC[3],
 {
     if (d.precision == 32) pair_go<float>(d, colour, eC, T, s);
     else pair_go<double>(d, colour, eC, T, s);
-    *blocks = cdiv((uint64_t)(d.Nc / 2), kThreads);
+    *blocks = cdiv((uint64_t)d.Nc, kThreads);
     return hipGetLastError();
 }
 
@@ -660,11 +813,11 @@ hipError_t launch_measure(const DevLattice& d, hipStream_t s, int64_t* blocks)
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t black_blocks, int64_t part_blocks,
-                           int flags, double T, hipStream_t s)
+hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t black_blocks, int fin, double T,
+                           hipStream_t s)
 {
     finalize_kernel<<<1, kThreads, 0, s>>>(d.st, d.part, d.cnt, (uint32_t)d.max_blocks, (uint32_t)red_blocks,
-                                            (uint32_t)black_blocks, (uint32_t)part_blocks, flags, T, (double)d.N);
+                                            (uint32_t)black_blocks, fin, T, (double)d.N);
     return hipGetLastError();
 }
 
