@@ -1,0 +1,140 @@
+"""Measurement protocols built on the sweep library.
+
+``mt_sweep`` runs the increasing-temperature protocol of Sec. 3 (state carried
+from one temperature to the next): at each T, equilibration sweeps, then
+sampled sweeps split into blocks.  Each block is averaged on the device (the
+accumulators are reset between blocks), so the standard errors come from
+batch means, which account for the autocorrelation of the chain.  It
+reports m(T) (Eq. 3's order parameter), E/N and the susceptibilities of
+Eq. 6.
+
+``constrained_scan`` runs the constrained algorithm (Table A2) over a grid of
+constraint directions and temperatures and reports the anisotropy energy and
+torque per spin.
+
+    python -m paper_2103_03517_amd.protocols mt --precision 32 --size 256
+"""
+import argparse
+import json
+import math
+import sys
+
+import numpy as np
+
+from . import Lattice
+
+
+def _block_stats(blocks, n, T):
+    """Combine equal-length blocks: means, batch-means standard errors, and
+    the susceptibility of the whole window (within-block variance plus the
+    variance of the block means)."""
+    mean_m = np.array([b["mean_m"] for b in blocks])        # (nb, 4)
+    var_m = np.array([b["var_m"] for b in blocks])
+    mean_e = np.array([b["mean_E"] for b in blocks])
+    nb = len(blocks)
+    m = mean_m.mean(axis=0)
+    se_m = mean_m.std(axis=0, ddof=1) / math.sqrt(nb) if nb > 1 else np.full(4, np.nan)
+    var_tot = var_m.mean(axis=0) + mean_m.var(axis=0)
+    chi = n * var_tot / T
+    chi_b = n * (var_m + (mean_m - m) ** 2) / T
+    se_chi = chi_b.std(axis=0, ddof=1) / math.sqrt(nb) if nb > 1 else np.full(4, np.nan)
+    e = float(mean_e.mean())
+    se_e = float(mean_e.std(ddof=1) / math.sqrt(nb)) if nb > 1 else float("nan")
+    return {"T": T, "m": m.tolist(), "se_m": se_m.tolist(), "E": e, "se_E": se_e,
+            "chi": chi.tolist(), "se_chi": se_chi.tolist(), "blocks": nb}
+
+
+def mt_sweep(temps, size=256, precision=32, equil=2000, samples=4000, block=200, seed=7,
+             init="random", J=1.0, Ku=0.005, eu=(0.0, 0.0, 1.0), instance=0, log=None):
+    """m(T), E(T), chi(T) along an ascending temperature list, one lattice."""
+    g = Lattice(size, size, size, precision=precision, J=J, Ku=Ku, eu=eu, seed=seed,
+                instance=instance, init=init)
+    out = []
+    for T in temps:
+        g.sweep(T, equil)
+        blocks = []
+        for _ in range(max(samples // block, 1)):
+            g.reset_stats()
+            g.sweep(T, block, sample=True)
+            blocks.append(g.observables())
+        r = _block_stats(blocks, g.n, T)
+        r["theta_deg"] = blocks[-1]["theta_deg"]
+        out.append(r)
+        if log:
+            log(f"T={T:.3f} m={r['m'][0]:.6f}+-{r['se_m'][0]:.1e} chi_l={r['chi'][0]:.4g} "
+                f"E/N={r['E']:.6f} theta={r['theta_deg']}")
+    g.close()
+    return out
+
+
+def ec_of(theta_deg, phi_deg):
+    t, p = math.radians(theta_deg), math.radians(phi_deg)
+    return (math.sin(t) * math.cos(p), math.sin(t) * math.sin(p), math.cos(t))
+
+
+def constrained_scan(thetas, phis, temps, size=128, precision=32, sweeps=3000, equil=1000,
+                     seed=3, Kc=0.05, Ku=0.0, J=1.0, log=None):
+    """Anisotropy energy and torque per spin with the moment held along
+    e_C(theta, phi), each run started along e_C."""
+    out = []
+    run = 0
+    for phi in phis:
+        for T in temps:
+            for th in thetas:
+                ec = ec_of(th, phi)
+                g = Lattice(size, size, size, precision=precision, J=J, Kc=Kc, Ku=Ku, seed=seed,
+                            instance=run, init="aligned", init_dir=ec)
+                g.constrained_sweep(T, ec, equil)
+                g.constrained_sweep(T, ec, sweeps - equil, sample=True)
+                o = g.observables()
+                g.close()
+                r = {"theta": th, "phi": phi, "T": T, "E_anis": o["mean_Eanis"],
+                     "E": o["mean_E"], "torque": o["mean_torque"], "m": o["mean_m"][0]}
+                out.append(r)
+                run += 1
+                if log:
+                    log(f"phi={phi} T={T} theta={th} E_anis={r['E_anis']:.6e} "
+                        f"torque={np.round(r['torque'], 7).tolist()}")
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("mt", help="increasing-temperature m(T) protocol")
+    a.add_argument("--size", type=int, default=256)
+    a.add_argument("--precision", type=int, default=32)
+    a.add_argument("--tmin", type=float, default=0.1)
+    a.add_argument("--tmax", type=float, default=1.6)
+    a.add_argument("--points", type=int, default=16)
+    a.add_argument("--equil", type=int, default=2000)
+    a.add_argument("--samples", type=int, default=4000)
+    a.add_argument("--block", type=int, default=200)
+    a.add_argument("--seed", type=int, default=7)
+    a.add_argument("--init", default="random", choices=["random", "aligned"])
+    a.add_argument("--Ku", type=float, default=0.005)
+    c = sub.add_parser("constrained", help="constrained-direction scan")
+    c.add_argument("--size", type=int, default=128)
+    c.add_argument("--precision", type=int, default=32)
+    c.add_argument("--sweeps", type=int, default=3000)
+    c.add_argument("--equil", type=int, default=1000)
+    c.add_argument("--Kc", type=float, default=0.05)
+    args = ap.parse_args(argv)
+
+    def log(s):
+        print(s, file=sys.stderr, flush=True)
+
+    if args.cmd == "mt":
+        temps = np.linspace(args.tmin, args.tmax, args.points).tolist()
+        res = mt_sweep(temps, size=args.size, precision=args.precision, equil=args.equil,
+                       samples=args.samples, block=args.block, seed=args.seed, init=args.init,
+                       Ku=args.Ku, log=log)
+    else:
+        res = constrained_scan(list(range(0, 91, 10)), [0, 45], [0.2 * k for k in range(1, 8)],
+                               size=args.size, precision=args.precision, sweeps=args.sweeps,
+                               equil=args.equil, Kc=args.Kc, log=log)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
