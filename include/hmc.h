@@ -105,8 +105,8 @@ typedef struct {
 } hmc_obs;
 
 /* Per-kernel timing collected with HIP events on the handle's stream while
- * timing is enabled.  Kinds: 0 = standard colour pass, 1 = constrained pair
- * pass, 2 = reductions (the per-sweep finalize: cone angle, counters,
+ * timing is enabled.  Kinds: 0 = standard colour pass, 1 = constrained sweep
+ * kernels (neighbour sums and pair passes), 2 = reductions (the per-sweep finalize: cone angle, counters,
  * accumulators; and the measurement of the current spins),
  * 3 = initialisation. */
 typedef struct {
@@ -115,7 +115,9 @@ typedef struct {
 } hmc_timing;
 
 /* Size in bytes of the device workspace for these parameters, 0 if the
- * parameters are invalid. */
+ * parameters are invalid: 36 bytes per spin at FP32 (72 at FP64) -- the
+ * spins, and the working copy and neighbour sums of constrained sweeps --
+ * plus a few MB of reduction partials. */
 size_t hmc_workspace_bytes(const hmc_params* p);
 
 /* Validates p, lays the lattice out in dev_ws (device memory, 256-byte
@@ -137,7 +139,9 @@ int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes,
 int hmc_sweep(hmc_lattice* L, double T, int32_t n_sweeps, int32_t sample);
 
 /* Enqueues n_sweeps iterations of the parallel constrained algorithm of
- * Table A2 with constraint direction eC (non-zero, normalised inside):
+ * Table A2 with constraint direction eC (non-zero, normalised inside).  The
+ * call works on a site-contiguous copy of the spins in the workspace (made
+ * at the start of the call, copied back at its end):
  * M_L = sum_i S_i . eC taken once at the start of each sweep, each colour
  * shuffled by a keyed permutation, consecutive shuffled spins paired, the
  * second spin of a pair compensating the first one's transverse change,

@@ -52,7 +52,7 @@ class Timing(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int64 * 4), ("total_ms", ctypes.c_double * 4)]
 
 
-TIMING_KINDS = ("pass", "pair_pass", "reduce", "init")
+TIMING_KINDS = ("pass", "constrained", "reduce", "other")
 
 # every function declared in include/hmc.h
 SYMBOLS = ("hmc_workspace_bytes", "hmc_init_lattice", "hmc_sweep", "hmc_constrained_sweep",

@@ -24,7 +24,7 @@ constexpr uint32_t kStateMagic = 0x484D4331u;  // "HMC1"
 constexpr size_t kMaxEvents = 16384;           // timing event pairs before a flush
 
 struct Layout {
-    size_t pitch, off_state, off_c1, off_part, off_cnt, total;
+    size_t pitch, off_aos, off_nbs, off_state, off_c1, off_part, off_cnt, total;
     int64_t max_blocks;
 };
 
@@ -78,6 +78,12 @@ Layout layout_for(const hmc_params* p)
     const size_t rs = p->precision / 8;
     L.pitch = align_up(Nc * rs, hmc::kAlign);
     size_t off = 6 * L.pitch;
+    // constrained sweeps: AoS working copy of both colours and the neighbour
+    // sums of one colour, 4 reals per site
+    L.off_aos = off;
+    off += align_up(2 * Nc * 4 * rs, hmc::kAlign);
+    L.off_nbs = off;
+    off += align_up(Nc * 4 * rs, hmc::kAlign);
     L.off_state = off;
     off += align_up(sizeof(DevState), hmc::kAlign);
     L.off_c1 = off;
@@ -183,7 +189,7 @@ int measure(hmc_lattice* L)
     int st = launch(L, 2, "measure kernel", [&] { return hmc::launch_measure(L->d, L->stream, &nb); });
     if (st == HMC_OK)
         st = launch(L, 2, "finalize kernel", [&] {
-            return hmc::launch_finalize(L->d, 0, nb, hmc::kFinObs | hmc::kFinTorque, 0.0, L->stream);
+            return hmc::launch_finalize(L->d, 0, 0, nb, hmc::kFinObs | hmc::kFinTorque, 0.0, L->stream);
         });
     if (st == HMC_OK) L->m_valid = true;
     return st;
@@ -235,6 +241,8 @@ int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes, void* h
     d.Nc = d.N / 2;
     d.pitch = lay.pitch;
     d.spins = base;
+    d.aos = base + lay.off_aos;
+    d.nbs = base + lay.off_nbs;
     d.st = reinterpret_cast<DevState*>(base + lay.off_state);
     d.c1tab = p->precision == 64 ? static_cast<const void*>(base + lay.off_c1)
                                  : static_cast<const void*>(base + lay.off_c1 + 181 * sizeof(double));
@@ -299,7 +307,7 @@ int hmc_sweep(hmc_lattice* L, double T, int32_t n_sweeps, int32_t sample)
         if (st == HMC_OK)
             st = launch(L, 2, "finalize kernel", [&] {
                 const int fin = hmc::kFinCounts | (obs ? (hmc::kFinObs | hmc::kFinSample) : 0);
-                return hmc::launch_finalize(L->d, nr, nb, fin, T, L->stream);
+                return hmc::launch_finalize(L->d, nr, nb, obs ? nb : 0, fin, T, L->stream);
             });
         if (st != HMC_OK) return st;
         L->m_valid = obs;
@@ -315,26 +323,31 @@ int hmc_constrained_sweep(hmc_lattice* L, double T, const double eC[3], int32_t 
     if (n_sweeps < 0) return fail(L, HMC_EINVAL, "n_sweeps must be >= 0");
     const double n = sqrt(eC[0] * eC[0] + eC[1] * eC[1] + eC[2] * eC[2]);
     const double e[3] = {eC[0] / n, eC[1] / n, eC[2] / n};
-    if (n_sweeps > 0 && !L->m_valid) {
+    if (n_sweeps == 0) return HMC_OK;
+    if (!L->m_valid) {
         int st = measure(L);
         if (st != HMC_OK) return st;
     }
-    for (int32_t it = 0; it < n_sweeps; ++it) {
-        int64_t nr = 0, nb = 0;
-        int st = launch(L, 1, "red pair pass",
-                        [&] { return hmc::launch_pair_pass(L->d, 0, e, T, L->stream, &nr); });
-        if (st == HMC_OK)
-            st = launch(L, 1, "black pair pass",
-                        [&] { return hmc::launch_pair_pass(L->d, 1, e, T, L->stream, &nb); });
+    using hmc::launch_constrained;
+    int64_t nb = 0;
+    auto step = [&](int kind, int which, const char* what) {
+        return launch(L, kind, what, [&] { return launch_constrained(L->d, which, e, T, L->stream, &nb); });
+    };
+    int st = step(3, hmc::kAosIn, "copy to the AoS working copy");
+    for (int32_t it = 0; it < n_sweeps && st == HMC_OK; ++it) {
+        st = step(1, hmc::kNbRed, "red neighbour sums");
+        if (st == HMC_OK) st = step(1, hmc::kPairRed, "red pair pass");
+        if (st == HMC_OK) st = step(1, hmc::kNbBlack, "black neighbour sums");
+        if (st == HMC_OK) st = step(1, hmc::kPairBlack, "black pair pass");
         if (st == HMC_OK)
             st = launch(L, 2, "finalize kernel", [&] {
                 const int fin = hmc::kFinCounts | hmc::kFinObs | hmc::kFinTorque | (sample ? hmc::kFinSample : 0);
-                return hmc::launch_finalize(L->d, nr, nb, fin, T, L->stream);
+                return hmc::launch_finalize(L->d, nb, nb, 2 * nb, fin, T, L->stream);
             });
-        if (st != HMC_OK) return st;
-        L->m_valid = true;
     }
-    return HMC_OK;
+    if (st == HMC_OK) st = step(3, hmc::kAosOut, "copy back from the AoS working copy");
+    if (st == HMC_OK) L->m_valid = true;
+    return st;
 }
 
 int hmc_observables(hmc_lattice* L, hmc_obs* out)

@@ -62,6 +62,8 @@ struct DevLattice {
     void* spins;              // [colour][component][Nc] of float or double
     DevState* st;
     const void* c1tab;        // 181 reals: 1 - cos(theta) for theta in degrees
+    void* aos;                // constrained sweeps: [colour][Nc] 4-vectors of the spins
+    void* nbs;                // constrained sweeps: [Nc] 4-vectors of neighbour sums
     double* part;             // [max_blocks][kNumPart]
     uint32_t* cnt;            // [2][max_blocks]
     int64_t max_blocks;
@@ -76,13 +78,16 @@ struct DevLattice {
 hipError_t launch_init(const DevLattice& d, hipStream_t s);
 hipError_t launch_pass(const DevLattice& d, int colour, bool obs, int spt, int zc, double T, hipStream_t s,
                        int64_t* blocks);
-hipError_t launch_pair_pass(const DevLattice& d, int colour, const double eC[3], double T, hipStream_t s,
-                            int64_t* blocks);
+// Steps of a constrained call: copy the spins into the AoS working copy, the
+// neighbour sums of colour 0 or 1, the pair pass of colour 0 or 1, copy back.
+enum ConstrainedStep { kAosIn = 0, kNbRed, kPairRed, kNbBlack, kPairBlack, kAosOut };
+hipError_t launch_constrained(const DevLattice& d, int step, const double eC[3], double T, hipStream_t s,
+                              int64_t* blocks);
 hipError_t launch_measure(const DevLattice& d, hipStream_t s, int64_t* blocks);
-// Reduces the results of the colour-1 launch (black_blocks work-groups; for
-// the counts also the red_blocks of the colour-0 launch) into the state.
-hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t black_blocks, int fin, double T,
-                           hipStream_t s);
+// Reduces the counts of the colour-0 (red_blocks) and colour-1 (black_blocks)
+// launches and the partials of part_blocks work-groups into the state.
+hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t black_blocks, int64_t part_blocks,
+                           int fin, double T, hipStream_t s);
 // Number of work-groups of the standard pass for a launch shape.
 int64_t pass_blocks(const DevLattice& d, int spt, int zc);
 // Dynamic LDS bytes of the standard pass for a launch shape.

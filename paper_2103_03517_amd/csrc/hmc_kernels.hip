@@ -243,7 +243,7 @@ __device__ __forceinline__ void block_end(const KArgs<R>& a, int colour, uint32_
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void finalize_kernel(DevState* st, const double* part, const uint32_t* cnt,
                                                             uint32_t cnt_stride, uint32_t nred, uint32_t nblack,
-                                                            int fin, double T, double N)
+                                                            uint32_t npart, int fin, double T, double N)
 {
     __shared__ double scratch[5 * (kNumPart + 1)];
     const uint32_t t = threadIdx.x;
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(DevState* st, const 
     }
     if (fin & kFinObs) {
         // each thread takes whole 96-byte records: six independent 16-byte loads
-        for (uint32_t i = t; i < nblack; i += kThreads) {
+        for (uint32_t i = t; i < npart; i += kThreads) {
             const double2* p = reinterpret_cast<const double2*>(part + (size_t)i * kNumPart);
 #pragma unroll
             for (int k = 0; k < kNumPart / 2; ++k) {
@@ -597,24 +597,122 @@ __device__ __forceinline__ void gather_neighbours(const KArgs<R>& a, const Array
 }
 
 // ---------------------------------------------------------------------------
-// Constrained pair pass (Table A2, ConstrainedMonteCarlo_ParallelPass) of
-// colour C.  The shuffled order pi of the colour indices is a keyed
-// bijection evaluated inline (nothing is stored); pair k is
-// (pi(2k), pi(2k+1)).  One thread per colour index a: the thread whose a is
-// the first spin of its pair (pi^-1(a) even) runs the pair move, so the first
-// spin and its neighbours are read coalesced and only the partner is a
-// random gather.  M_L is the moment along eC at the start of the sweep (one
-// value for both colours, as in the paper).  OBS (black pass) fuses the
-// observables over the two black sites and their red x-partners; since pi is
-// a bijection every site is covered once.
+// Constrained sweep (Table A2).  A constrained call works on an AoS copy of
+// the spins (one 16-byte FP32 / 32-byte FP64 entry per site, both colours),
+// made on entry and copied back on exit, so that a random gather is one
+// cache line instead of three.  Before each colour pass the neighbour sums of
+// that colour are precomputed (the other colour does not change during the
+// pass, so they are exact); the pair pass then needs, for each spin of a
+// pair, its own entry and its neighbour sum: two lines for the random
+// partner instead of twenty-one.
 // ---------------------------------------------------------------------------
-template <typename R, int C, bool OBS>
-__global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, const V3<R> ec, const uint32_t half,
-                                                        const uint32_t mask, const R scale)
+template <typename R> struct Vec4T;
+template <> struct Vec4T<float> { using type = float4; };
+template <> struct Vec4T<double> { using type = double4; };
+template <typename R> using Vec4 = typename Vec4T<R>::type;
+
+template <typename R>
+__device__ __forceinline__ V3<R> ld4(const Vec4<R>* p, uint32_t i)
 {
-    __shared__ double scratch[8 * kNumPart];
-    constexpr uint32_t rs = sizeof(R);
-    const Arrays<R> g(a);
+    const Vec4<R> q = p[i];
+    return V3<R>{q.x, q.y, q.z};
+}
+
+template <typename R>
+__device__ __forceinline__ void st4(Vec4<R>* p, uint32_t i, const V3<R>& v)
+{
+    Vec4<R> q;
+    q.x = v.x;
+    q.y = v.y;
+    q.z = v.z;
+    q.w = R(0);
+    p[i] = q;
+}
+
+// SoA -> AoS (to_aos) or AoS -> SoA, both colours; aos[c * Nc + k].
+template <typename R, bool TO_AOS>
+__global__ __launch_bounds__(kThreads) void aos_copy_kernel(const KArgs<R> a, Vec4<R>* aos)
+{
+    const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
+    const int c = blockIdx.y;
+    if (k >= a.Nc) return;
+    const size_t i = (size_t)c * a.Nc + k;
+    if (TO_AOS) {
+        st4<R>(aos + (size_t)c * a.Nc, k, V3<R>{a.s[c][0][k], a.s[c][1][k], a.s[c][2][k]});
+    } else {
+        const Vec4<R> q = aos[i];
+        a.s[c][0][k] = q.x;
+        a.s[c][1][k] = q.y;
+        a.s[c][2][k] = q.z;
+    }
+}
+
+// Colour indices of the six neighbours (other colour) of colour index k of
+// colour C, in the order x-, x+, y-, y+, z-, z+.
+template <int C>
+__device__ __forceinline__ void neighbour_indices(uint32_t k, uint32_t hx, uint32_t ny, uint32_t nz, uint32_t P,
+                                                  uint32_t (&nb)[6])
+{
+    const uint32_t kx = k % hx, r = k / hx;
+    const uint32_t y = r % ny, z = r / ny;
+    const uint32_t p = (y + z + (uint32_t)C) & 1u;
+    const uint32_t row = k - kx;
+    const uint32_t d = p ? (kx == hx - 1 ? row : k + 1) : (kx == 0 ? row + hx - 1 : k - 1);
+    const uint32_t fz = P * z, inpl = kx + hx * y;
+    nb[0] = p ? k : d;
+    nb[1] = p ? d : k;
+    nb[2] = kx + hx * (y == 0 ? ny - 1 : y - 1) + fz;
+    nb[3] = kx + hx * (y == ny - 1 ? 0 : y + 1) + fz;
+    nb[4] = inpl + P * (z == 0 ? nz - 1 : z - 1);
+    nb[5] = inpl + P * (z == nz - 1 ? 0 : z + 1);
+}
+
+// Neighbour sums of colour C (from the AoS copy of the other colour).  With
+// OBS (C = 1, after the red pass) it also adds the one-site terms of every
+// red site (the same-index partner of black site k) to the observables.
+template <typename R, int C, bool OBS>
+__global__ __launch_bounds__(kThreads) void nbsum_kernel(const KArgs<R> a, const Vec4<R>* aos, Vec4<R>* nbs)
+{
+    __shared__ double scratch[5 * kNumPart];
+    const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
+    const Vec4<R>* other = aos + (size_t)(1 - C) * a.Nc;
+    Acc acc;
+    if (k < a.Nc) {
+        uint32_t id[6];
+        neighbour_indices<C>(k, a.hx, a.ny, a.nz, a.P, id);
+        V3<R> v[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[i] = ld4<R>(other, id[i]);
+        const V3<R> nb{((((v[0].x + v[1].x) + v[2].x) + v[3].x) + v[4].x) + v[5].x,
+                       ((((v[0].y + v[1].y) + v[2].y) + v[3].y) + v[4].y) + v[5].y,
+                       ((((v[0].z + v[1].z) + v[2].z) + v[3].z) + v[4].z) + v[5].z};
+        st4<R>(nbs, k, nb);
+        if (OBS) add_site<R, true>(acc, a.m, ld4<R>(other, k));
+    }
+    if (OBS) {
+        double vv[kNumPart] = {acc.M[0], acc.M[1], acc.M[2], acc.ex, acc.eu, acc.ec, acc.ez,
+                               acc.tq[0], acc.tq[1], acc.tq[2], 0.0, 0.0};
+        block_sum<kNumPart>(vv, scratch);
+        if (threadIdx.x < kNumPart) a.part[(size_t)blockIdx.x * kNumPart + threadIdx.x] = scratch[threadIdx.x];
+    }
+}
+
+// Pair pass of colour C.  The shuffled order pi of the colour indices is a
+// keyed bijection evaluated inline (nothing is stored); pair k is
+// (pi(2k), pi(2k+1)).  One thread per colour index a: the thread whose a is
+// the first spin of its pair (pi^-1(a) even) runs the pair move, so the
+// first spin is read coalesced and only the partner is a random gather.  M_L
+// is the moment along eC at the start of the sweep (one value for both
+// colours, as in the paper).  OBS (black pass) adds the two black sites and
+// their exchange with their final red neighbours; since pi is a bijection
+// every black site is covered once.  Results go to row part_base + block.
+template <typename R, int C, bool OBS>
+__global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R>* aos, const Vec4<R>* nbs,
+                                                        const V3<R> ec, const uint32_t half, const uint32_t mask,
+                                                        const R scale, const uint32_t part_base)
+{
+    __shared__ double scratch[5 * kNumPart];
+    Vec4<R>* own = aos + (size_t)C * a.Nc;
     const uint32_t ia = blockIdx.x * kThreads + threadIdx.x;
     const uint32_t sweep = (uint32_t)a.st->sweep;
     const R c1 = a.c1tab[a.st->theta];
@@ -630,12 +728,8 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, const 
     if ((pos & 1u) == 0u) {
         const uint32_t k = pos >> 1;
         const uint32_t ja = shuffle_index(pos + 1u, a.Nc, half, mask, key);
-        V3<R> nbi, nbj, pti, ptj;
-        uint32_t site_i, site_j;
-        gather_neighbours<R, C>(a, g, ia, nbi, pti, site_i);
-        gather_neighbours<R, C>(a, g, ja, nbj, ptj, site_j);
-        const V3<R> si = g.get(C, ia * rs, 0);
-        const V3<R> sj = g.get(C, ja * rs, 0);
+        const V3<R> si = ld4<R>(own, ia), nbi = ld4<R>(nbs, ia);
+        const V3<R> sj = ld4<R>(own, ja), nbj = ld4<R>(nbs, ja);
         const Rand4 rn = philox(sweep, k, 2u + (uint32_t)C, a.inst, a.key0, a.key1);
         const V3<R> ti = cone_move(si, Prim<R>::u01(rn.r0), Prim<R>::u01(rn.r1), c1);
 
@@ -660,19 +754,19 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, const 
         const V3<R> fi = ok ? ti : si;
         const V3<R> fj = ok ? tj : sj;
         if (ok) {
-            g.put(C, ia * rs, 0, ti);
-            g.put(C, ja * rs, 0, tj);
+            st4<R>(own, ia, ti);
+            st4<R>(own, ja, tj);
             nacc = 2;
         }
         if (OBS) {
             acc.ex += (double)(-m.J * dot(fi, nbi)) + (double)(-m.J * dot(fj, nbj));
             add_site<R, true>(acc, m, fi);
             add_site<R, true>(acc, m, fj);
-            add_site<R, true>(acc, m, pti);
-            add_site<R, true>(acc, m, ptj);
         }
     }
-    block_end<R, OBS>(a, C, blockIdx.x, nacc, acc, scratch);
+    KArgs<R> ra = a;
+    ra.part = a.part + (size_t)part_base * kNumPart;
+    block_end<R, OBS>(ra, C, blockIdx.x, nacc, acc, scratch);
 }
 
 // ---------------------------------------------------------------------------
@@ -709,7 +803,7 @@ int64_t max_blocks_for(int32_t nx, int32_t ny, int32_t nz)
     const uint64_t P = (uint64_t)(nx / 2) * (uint64_t)ny;
     const uint64_t Nc = P * (uint64_t)nz;
     const int64_t pass = (int64_t)cdiv(P, kThreads) * (int64_t)nz;
-    const int64_t gather = (int64_t)cdiv(Nc, kThreads);
+    const int64_t gather = 2 * (int64_t)cdiv(Nc, kThreads);   // neighbour-sum + pair partials
     return pass > gather ? pass : gather;
 }
 
@@ -780,27 +874,46 @@ hipError_t launch_pass(const DevLattice& d, int colour, bool obs, int spt, int z
 }
 
 template <typename R>
-static void pair_go(const DevLattice& d, int colour, const double eC[3], double T, hipStream_t s)
+static void constrained_go(const DevLattice& d, int step, const double eC[3], double T, hipStream_t s,
+                           int64_t* blocks)
 {
     const auto a = make_args<R>(d);
+    Vec4<R>* aos = static_cast<Vec4<R>*>(d.aos);
+    Vec4<R>* nbs = static_cast<Vec4<R>*>(d.nbs);
     const uint32_t n = (uint32_t)d.Nc;
+    const uint32_t grid = cdiv(n, kThreads);
+    *blocks = grid;
+    if (step == kAosIn) {
+        aos_copy_kernel<R, true><<<dim3(grid, 2), kThreads, 0, s>>>(a, aos);
+        return;
+    }
+    if (step == kAosOut) {
+        aos_copy_kernel<R, false><<<dim3(grid, 2), kThreads, 0, s>>>(a, aos);
+        return;
+    }
+    if (step == kNbRed) {
+        nbsum_kernel<R, 0, false><<<grid, kThreads, 0, s>>>(a, aos, nbs);
+        return;
+    }
+    if (step == kNbBlack) {
+        nbsum_kernel<R, 1, true><<<grid, kThreads, 0, s>>>(a, aos, nbs);
+        return;
+    }
     uint32_t bits = 2;
     while (bits < 32 && (1ull << bits) < n) bits += 2;
     const uint32_t half = bits / 2;
     const uint32_t mask = half >= 32 ? 0xFFFFFFFFu : ((1u << half) - 1u);
     const V3<R> ec{(R)eC[0], (R)eC[1], (R)eC[2]};
-    const uint32_t grid = cdiv(n, kThreads);
     const R scale = Prim<R>::scale_for(T);
-    if (colour == 0) pair_kernel<R, 0, false><<<grid, kThreads, 0, s>>>(a, ec, half, mask, scale);
-    else pair_kernel<R, 1, true><<<grid, kThreads, 0, s>>>(a, ec, half, mask, scale);
+    if (step == kPairRed) pair_kernel<R, 0, false><<<grid, kThreads, 0, s>>>(a, aos, nbs, ec, half, mask, scale, 0u);
+    else pair_kernel<R, 1, true><<<grid, kThreads, 0, s>>>(a, aos, nbs, ec, half, mask, scale, grid);
 }
 
-hipError_t launch_pair_pass(const DevLattice& d, int colour, const double eC[3], double T, hipStream_t s,
-                            int64_t* blocks)
+hipError_t launch_constrained(const DevLattice& d, int step, const double eC[3], double T, hipStream_t s,
+                              int64_t* blocks)
 {
-    if (d.precision == 32) pair_go<float>(d, colour, eC, T, s);
-    else pair_go<double>(d, colour, eC, T, s);
-    *blocks = cdiv((uint64_t)d.Nc, kThreads);
+    if (d.precision == 32) constrained_go<float>(d, step, eC, T, s, blocks);
+    else constrained_go<double>(d, step, eC, T, s, blocks);
     return hipGetLastError();
 }
 
@@ -813,11 +926,11 @@ hipError_t launch_measure(const DevLattice& d, hipStream_t s, int64_t* blocks)
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t black_blocks, int fin, double T,
-                           hipStream_t s)
+hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t black_blocks, int64_t part_blocks,
+                           int fin, double T, hipStream_t s)
 {
     finalize_kernel<<<1, kThreads, 0, s>>>(d.st, d.part, d.cnt, (uint32_t)d.max_blocks, (uint32_t)red_blocks,
-                                            (uint32_t)black_blocks, fin, T, (double)d.N);
+                                            (uint32_t)black_blocks, (uint32_t)part_blocks, fin, T, (double)d.N);
     return hipGetLastError();
 }
 

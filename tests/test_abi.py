@@ -60,12 +60,13 @@ def test_validation(hmc, kw, status):
 
 def test_workspace_size_and_too_small(hmc):
     L = hmc.lib()
+    # spins (12 B) + constrained working copy and neighbour sums (24 B) per spin
     p = hmc.make_params(256, 256, 256, precision=32)
     n32 = L.hmc_workspace_bytes(ctypes.byref(p))
-    assert n32 >= 256 ** 3 * 12
-    assert n32 < 256 ** 3 * 12 * 1.05
+    assert 256 ** 3 * 36 <= n32 < 256 ** 3 * 36 * 1.03
     p64 = hmc.make_params(256, 256, 256, precision=64)
-    assert L.hmc_workspace_bytes(ctypes.byref(p64)) >= 256 ** 3 * 24
+    n64 = L.hmc_workspace_bytes(ctypes.byref(p64))
+    assert 256 ** 3 * 72 <= n64 < 256 ** 3 * 72 * 1.03
     h = ctypes.c_void_p()
     # a workspace smaller than required is refused before any device call
     assert L.hmc_init_lattice(ctypes.byref(p), ctypes.c_void_p(4096), 1024, None,
