@@ -8,8 +8,11 @@ spins: J = 1, Ku = 0.005 along z, uniform random start from seed 7, T = 1.0.
 The lattice is resident in HBM before the timed region starts.  The line
 printed also carries the same sweep in FP64, the constrained pair sweep at
 128^3 (Kc = 0.05), a 384^3 FP32 control that does not fit the 256 MB
-Infinity Cache, the roofline of the dominant kernel and the serial CPU
-reference timed on this host.
+Infinity Cache, the batched form (64 independent m(T) jobs of uneven sizes
+advanced together, FP32, each job checked against the same job run in FP64),
+a serving run (Poisson arrivals of m(T) jobs at 20 per second, continuous
+batching under an HBM budget, p50/p99 latency), the roofline of the dominant
+kernel and the serial CPU reference timed on this host.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
 """
@@ -120,6 +123,87 @@ def time_leg(H, torch, shape, precision, T, steps, warmup, constrained=False, **
     return out
 
 
+def batch_leg(sequential=False):
+    """64 independent m(T) jobs (edges from {48, 64, 80, 96, 128}, T uniform in
+    [0.05, 1.7), Ku = 0.01, aligned start, 1000 + 4000 sweeps, blocks of 200)
+    advanced as one FP32 batch, then the same jobs in FP64 for the precision
+    check.  Jobs/s counts whole jobs from the first sweep to the last read."""
+    import torch
+    from paper_2103_03517_amd import protocols as P
+    jobs = P.c4_jobs(64)
+    log(f"leg 5: batched m(T) jobs, {len(jobs)} lattices, FP32 (autotuned launch shapes)")
+    r32, i32 = P.batched_mt(jobs, 32, log=log)
+    log("  the same jobs in FP64")
+    r64, i64 = P.batched_mt(jobs, 64, tune=False, log=log)
+    cmp = P.compare_precisions(r32, r64)
+    shapes = {}
+    for (e, _), sh in zip(jobs, i32["shapes"]):
+        shapes[f"{e}^3"] = list(sh)
+    out = {
+        "workload": "64 independent periodic cubic lattices, edges drawn from {48,64,80,96,128} "
+                    "(seed 4), T ~ U(0.05, 1.7), J=1, Ku=0.01 along z, aligned start, "
+                    "1000 equilibration + 4000 sampled sweeps per job, FP64 accumulators",
+        "jobs": len(jobs), "spins": i32["spins"], "sweeps_per_job": 5000,
+        "jobs_per_s": len(jobs) / i32["run_s"], "updates_per_s": i32["updates"] / i32["run_s"],
+        "wall_s": i32["run_s"], "tune_s": i32["tune_s"], "launch_shapes": shapes,
+        "fp64_jobs_per_s": len(jobs) / i64["run_s"], "fp64_updates_per_s": i64["updates"] / i64["run_s"],
+        "precision": {"max_abs_dm": max(c["dm"] for c in cmp),
+                      "jobs_within_1e-3": sum(c["dm"] <= 1e-3 for c in cmp),
+                      "jobs_within_3se": sum(c["dm_over_se"] <= 3.0 for c in cmp),
+                      "max_dm_over_se": max(c["dm_over_se"] for c in cmp),
+                      "jobs": len(cmp)},
+    }
+    log(f"  FP32 {out['jobs_per_s']:.2f} jobs/s ({out['updates_per_s'] / 1e9:.1f} G updates/s), "
+        f"FP64 {out['fp64_jobs_per_s']:.2f} jobs/s; |dm| max {out['precision']['max_abs_dm']:.2e}, "
+        f"{out['precision']['jobs_within_1e-3']}/{len(cmp)} within 1e-3, "
+        f"{out['precision']['jobs_within_3se']}/{len(cmp)} within 3 SE")
+    if sequential:
+        import time
+        import paper_2103_03517_amd as H
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, (e, t) in enumerate(jobs):
+            g = H.Lattice(e, e, e, precision=32, J=1.0, Ku=0.01, seed=4, instance=i, init="aligned")
+            g.sweep(t, 1000)
+            for _ in range(20):
+                g.sweep(t, 200, sample=True)
+                g.observables()
+            g.close()
+        torch.cuda.synchronize()
+        out["sequential_jobs_per_s"] = len(jobs) / (time.perf_counter() - t0)
+        log(f"  one lattice at a time: {out['sequential_jobs_per_s']:.2f} jobs/s")
+    return out
+
+
+def serve_leg(rate=20.0, seconds=10.0):
+    """Poisson arrivals (seed 5) of m(T) jobs on 32^3..192^3 lattices, 200 +
+    800 sweeps each, served by the continuous-batching loop in FP32; then the
+    same jobs all at once (saturation) for the capacity in jobs/s."""
+    from paper_2103_03517_amd import serving as S
+    jobs = S.poisson_jobs(rate, seconds)
+    srv = S.Server(precision=32, hbm_budget=32 << 30, quantum=50)
+    log(f"leg 6: serving {len(jobs)} m(T) jobs arriving at {rate}/s over {seconds} s")
+    shapes = srv.tune_shapes(sorted({j.edge for j in jobs}))
+    done = srv.run(jobs)
+    live = S.latency_summary(done)
+    log(f"  p50 {live['p50_s'] * 1e3:.1f} ms, p99 {live['p99_s'] * 1e3:.1f} ms, "
+        f"max active {srv.stats['max_active']}")
+    sat = S.Server(precision=32, hbm_budget=32 << 30, quantum=50, shapes=shapes)
+    done2 = sat.run(S.poisson_jobs(rate, seconds), realtime=False)
+    cap = S.latency_summary(done2)
+    log(f"  saturation: {cap['jobs_per_s']:.1f} jobs/s, {cap['updates_per_s'] / 1e9:.1f} G updates/s")
+    return {"workload": f"Poisson arrivals at {rate}/s for {seconds} s (seed 5): m(T) jobs on edge^3 "
+                        "periodic lattices, edge uniform in {32,48,64,96,128,160,192}, T ~ U(0.05, 1.7), "
+                        "Ku=0.01, 200 equilibration + 800 sampled sweeps (blocks of 100), FP32, "
+                        "HBM budget 32 GiB, at most 64 jobs in flight",
+            "offered_jobs": len(jobs), "completed": live["jobs"],
+            "p50_latency_s": live["p50_s"], "p99_latency_s": live["p99_s"], "max_latency_s": live["max_s"],
+            "jobs_per_s": live["jobs_per_s"], "max_active": srv.stats["max_active"],
+            "ticks": srv.stats["ticks"], "batch_rebuilds": srv.stats["rebuilds"],
+            "saturation_jobs_per_s": cap["jobs_per_s"], "saturation_updates_per_s": cap["updates_per_s"],
+            "saturation_p99_latency_s": cap["p99_s"]}
+
+
 def cpu_baseline(sweeps):
     """The serial FP64 reference (one thread) on a bounded sample of the same
     workload: `sweeps` sampled sweeps of the 256^3 lattice from seed 7."""
@@ -142,6 +226,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference leg")
     ap.add_argument("--main-only", action="store_true", help="only the 256^3 FP32 leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-jobs leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--batch-sequential", action="store_true",
+                    help="also run the batched jobs one lattice at a time, for comparison")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run a few 256^3 FP32 sweeps and nothing else (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -197,6 +285,13 @@ def main():
                                           max(W // 3, 5))
         log(f"  {extra['fp32_384cubed']['value'] / 1e9:.2f} G updates/s")
 
+    batched = None
+    if not args.main_only and not args.no_batch:
+        batched = batch_leg(args.batch_sequential)
+    served = None
+    if not args.main_only and not args.no_serve:
+        served = serve_leg()
+
     # roofline of the dominant kernel: the FP32 colour pass of leg 1
     pass_ms = main_leg["kernels_ms"]["pass"]
     alg = algorithmic_pass_bytes(n, 32)
@@ -247,6 +342,10 @@ def main():
     line["kernel_timing"] = ("per-kernel averages from HIP events recorded by the library on the "
                              f"lattice's stream over a second region of {main_leg['kernel_timing_steps']} "
                              "steps of the same workload")
+    if batched is not None:
+        line["batched"] = batched
+    if served is not None:
+        line["serving"] = served
     if cpu is not None:
         line["speedup_vs_cpu_baseline"] = main_leg["value"] / cpu["value"]
     print(json.dumps(line), flush=True)

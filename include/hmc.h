@@ -194,6 +194,91 @@ void hmc_destroy(hmc_lattice* L);
 const char* hmc_strerror(int status);
 const char* hmc_last_error(const hmc_lattice* L);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent lattices (the separate runs at many
+ * temperatures and sizes that Sec. 3 sweeps over, e.g. for m(T)) advanced
+ * together.  A batch sweep issues one launch per colour pass for every
+ * group of lattices that share a kernel variant (sites per thread and
+ * halo width: at most 9 groups, usually one or two), and one finalize
+ * launch in which work-group i folds lattice i's counts and sums.  Each
+ * lattice keeps its own spins, cone angle, sweep counter and
+ * accumulators, and each of its tiles runs exactly as in hmc_sweep, so
+ * with the same launch shape a lattice in a batch ends bit for bit where
+ * it would alone (random numbers are keyed by the lattice's own seed and
+ * instance, not by its place in the batch).
+ *
+ * Ownership: the caller owns the lattices, which must outlive the batch,
+ * and a device workspace of hmc_batch_workspace_bytes(count) bytes
+ * (256-byte aligned) that holds the batch table and the per-lattice
+ * temperatures.  The library allocates the host handle, a small pinned
+ * staging buffer for the table uploads and, for graph replays, one
+ * capture stream; hmc_batch_destroy releases them.  All work goes to the
+ * stream of the lattices, which must be the same for all of them.
+ * ------------------------------------------------------------------------ */
+typedef struct hmc_batch hmc_batch;
+
+/* Device workspace for a batch of count (1 .. 65536) lattices; 0 if count
+ * is out of range.  About 0.4 KB per lattice. */
+size_t hmc_batch_workspace_bytes(int32_t count);
+
+/* Builds a batch over lattices[0 .. count-1] (distinct handles, one
+ * precision, one stream).  The launch shape of each lattice is the one set
+ * by hmc_set_launch (a later change is picked up by the next batch call).
+ * Errors: HMC_EINVAL (null, duplicate, mixed precision or stream),
+ * HMC_ENOMEM (workspace too small or misaligned), HMC_EHIP. */
+int hmc_batch_create(hmc_lattice* const* lattices, int32_t count, void* dev_ws, size_t ws_bytes,
+                     hmc_batch** out);
+
+/* Enqueues n_sweeps standard sweeps (Table A1) of every lattice of the
+ * batch, lattice i at temperature T[i] (count values, each > 0 and
+ * finite); sample as in hmc_sweep.  Observables are read per lattice with
+ * hmc_observables.  Errors: HMC_EINVAL, HMC_EHIP. */
+int hmc_batch_sweep(hmc_batch* B, const double* T, int32_t n_sweeps, int32_t sample);
+
+/* As hmc_batch_sweep, with a sample flag per lattice (sample[i] != 0:
+ * lattice i accumulates), so that lattices in different phases of their
+ * runs (equilibration, sampling) advance together.  The black pass computes
+ * the fused sums whenever any lattice samples.  Errors: HMC_EINVAL,
+ * HMC_EHIP. */
+int hmc_batch_sweep_each(hmc_batch* B, const double* T, const int32_t* sample, int32_t n_sweeps);
+
+/* Observables of every lattice: out[i] receives what hmc_observables
+ * gives for lattice i (the current spins are measured).  Synchronises the
+ * stream once.  Returns the first error of any lattice (HMC_ENUMERIC with
+ * all of out filled). */
+int hmc_batch_observables(hmc_batch* B, hmc_obs* out);
+
+/* Clears the accumulators of every lattice, as hmc_reset_stats does, with
+ * one kernel on the stream and without synchronising. */
+int hmc_batch_reset_stats(hmc_batch* B);
+
+/* Autotuner: for each distinct lattice size of the batch, in turn, times
+ * trial_sweeps (1 .. 1000) batch sweeps at temperatures T for every
+ * admissible launch shape (sites_per_thread 1, 2, 4 within the LDS
+ * budget; z_chunk 2 .. 64, powers of two up to nz) with the other sizes
+ * held, and keeps the fastest.  The chosen shapes are set on the lattices
+ * (hmc_get_launch reads them).  Every lattice's state is saved before and
+ * restored after (host copies), so tuning leaves the chains where they
+ * were.  Synchronises.  Errors: HMC_EINVAL, HMC_EHIP, HMC_ENOMEM (host). */
+int hmc_batch_tune(hmc_batch* B, const double* T, int32_t trial_sweeps);
+
+/* Graph replay: with sweeps_per_graph > 0, runs of that many sweeps are
+ * captured once (per sample flag) as a HIP graph on a private stream and
+ * replayed on the lattices' stream, which removes the per-launch host
+ * cost; sweeps_per_graph = 0 (the default) launches eagerly.  Replays do
+ * exactly the work of the eager launches.  Timing (below) uses eager
+ * launches.  Errors: HMC_EINVAL (negative or above 4096). */
+int hmc_batch_set_graph(hmc_batch* B, int32_t sweeps_per_graph);
+
+/* Per-launch timing of batch sweeps, kinds as in hmc_timing (0: colour
+ * passes, 2: finalize). */
+int hmc_batch_set_timing(hmc_batch* B, int32_t enable);
+int hmc_batch_read_timing(hmc_batch* B, hmc_timing* out);
+
+/* Waits for the stream and releases the handle (not the lattices). */
+void hmc_batch_destroy(hmc_batch* B);
+const char* hmc_batch_last_error(const hmc_batch* B);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ import os
 import numpy as np
 import torch
 
-__all__ = ["Lattice", "HmcError", "lib", "LIB_PATH", "SYMBOLS"]
+__all__ = ["Lattice", "Batch", "HmcError", "lib", "LIB_PATH", "SYMBOLS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhmc.so")
@@ -59,7 +59,10 @@ SYMBOLS = ("hmc_workspace_bytes", "hmc_init_lattice", "hmc_sweep", "hmc_constrai
            "hmc_observables", "hmc_reset_stats", "hmc_copy_spins", "hmc_state_bytes",
            "hmc_get_state", "hmc_set_state", "hmc_set_launch", "hmc_get_launch",
            "hmc_set_timing", "hmc_read_timing", "hmc_destroy", "hmc_strerror",
-           "hmc_last_error")
+           "hmc_last_error", "hmc_batch_workspace_bytes", "hmc_batch_create", "hmc_batch_sweep",
+           "hmc_batch_tune", "hmc_batch_set_graph", "hmc_batch_set_timing",
+           "hmc_batch_read_timing", "hmc_batch_destroy", "hmc_batch_last_error",
+           "hmc_batch_observables", "hmc_batch_reset_stats", "hmc_batch_sweep_each")
 
 _lib = None
 
@@ -108,6 +111,30 @@ def lib():
     L.hmc_strerror.argtypes = [i32]
     L.hmc_last_error.restype = ctypes.c_char_p
     L.hmc_last_error.argtypes = [vp]
+    L.hmc_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.hmc_batch_workspace_bytes.argtypes = [i32]
+    L.hmc_batch_create.restype = i32
+    L.hmc_batch_create.argtypes = [P(vp), i32, vp, ctypes.c_size_t, P(vp)]
+    L.hmc_batch_sweep.restype = i32
+    L.hmc_batch_sweep.argtypes = [vp, P(dbl), i32, i32]
+    L.hmc_batch_tune.restype = i32
+    L.hmc_batch_tune.argtypes = [vp, P(dbl), i32]
+    L.hmc_batch_set_graph.restype = i32
+    L.hmc_batch_set_graph.argtypes = [vp, i32]
+    L.hmc_batch_set_timing.restype = i32
+    L.hmc_batch_set_timing.argtypes = [vp, i32]
+    L.hmc_batch_read_timing.restype = i32
+    L.hmc_batch_read_timing.argtypes = [vp, P(Timing)]
+    L.hmc_batch_destroy.restype = None
+    L.hmc_batch_destroy.argtypes = [vp]
+    L.hmc_batch_last_error.restype = ctypes.c_char_p
+    L.hmc_batch_last_error.argtypes = [vp]
+    L.hmc_batch_observables.restype = i32
+    L.hmc_batch_observables.argtypes = [vp, P(Obs)]
+    L.hmc_batch_reset_stats.restype = i32
+    L.hmc_batch_reset_stats.argtypes = [vp]
+    L.hmc_batch_sweep_each.restype = i32
+    L.hmc_batch_sweep_each.argtypes = [vp, P(dbl), P(i32), i32]
     _lib = L
     return L
 
@@ -246,3 +273,88 @@ class Lattice:
         self._check(self._lib.hmc_read_timing(self._h, ctypes.byref(t)))
         return {k: {"count": int(t.count[i]), "total_ms": float(t.total_ms[i])}
                 for i, k in enumerate(TIMING_KINDS)}
+
+
+def _timing_dict(t):
+    return {k: {"count": int(t.count[i]), "total_ms": float(t.total_ms[i])}
+            for i, k in enumerate(TIMING_KINDS)}
+
+
+class Batch:
+    """Independent lattices (one precision, one stream) swept together: one
+    launch per colour pass and kernel variant, one finalize launch.  The
+    lattices stay usable on their own (observables, checkpoints, single
+    sweeps) and must outlive the batch."""
+
+    def __init__(self, lattices):
+        self._lib = lib()
+        self.lattices = list(lattices)
+        n = len(self.lattices)
+        nbytes = int(self._lib.hmc_batch_workspace_bytes(n))
+        handles = (ctypes.c_void_p * max(n, 1))(*[l._h for l in self.lattices])
+        dev = self.lattices[0].device if n else torch.device("cuda")
+        self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        h = ctypes.c_void_p()
+        st = self._lib.hmc_batch_create(handles, n, ctypes.c_void_p(self.workspace.data_ptr()),
+                                        nbytes, ctypes.byref(h))
+        if st != OK:
+            raise HmcError(st, self._lib.hmc_strerror(st).decode())
+        self._h = h
+
+    def _check(self, st):
+        if st != OK:
+            raise HmcError(st, self._lib.hmc_batch_last_error(self._h).decode())
+
+    def _temps(self, T):
+        T = np.broadcast_to(np.asarray(T, dtype=np.float64), (len(self.lattices),))
+        return (ctypes.c_double * len(T))(*[float(v) for v in T])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hmc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, T, n=1, sample=False):
+        """n standard sweeps of every lattice; T is one value or one per lattice."""
+        self._check(self._lib.hmc_batch_sweep(self._h, self._temps(T), int(n), int(bool(sample))))
+
+    def sweep_each(self, T, sample, n=1):
+        """n standard sweeps; sample[i] says whether lattice i accumulates."""
+        flags = (ctypes.c_int32 * len(self.lattices))(*[int(bool(v)) for v in sample])
+        self._check(self._lib.hmc_batch_sweep_each(self._h, self._temps(T), flags, int(n)))
+
+    def tune(self, T, trial_sweeps=4):
+        """Pick the launch shape of each lattice size by timing batch sweeps;
+        the chains are restored afterwards.  Returns the shapes per lattice."""
+        self._check(self._lib.hmc_batch_tune(self._h, self._temps(T), int(trial_sweeps)))
+        return [l.get_launch() for l in self.lattices]
+
+    def observables(self, check=True):
+        """Observables of every lattice (one synchronisation)."""
+        n = len(self.lattices)
+        o = (Obs * n)()
+        st = self._lib.hmc_batch_observables(self._h, o)
+        if check:
+            self._check(st)
+        return [_obs_dict(x) for x in o]
+
+    def reset_stats(self):
+        """Clear every lattice's accumulators (enqueued, no synchronisation)."""
+        self._check(self._lib.hmc_batch_reset_stats(self._h))
+
+    def set_graph(self, sweeps_per_graph):
+        self._check(self._lib.hmc_batch_set_graph(self._h, int(sweeps_per_graph)))
+
+    def set_timing(self, enable=True):
+        self._check(self._lib.hmc_batch_set_timing(self._h, int(bool(enable))))
+
+    def read_timing(self):
+        t = Timing()
+        self._check(self._lib.hmc_batch_read_timing(self._h, ctypes.byref(t)))
+        return _timing_dict(t)

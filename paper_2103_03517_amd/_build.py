@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhmc.so")
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, "hmc_api.cpp"), os.path.join(CSRC, "hmc_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "hmc_api.cpp"), os.path.join(CSRC, "hmc_batch.cpp"),
+           os.path.join(CSRC, "hmc_kernels.hip")]
 ARCH = os.environ.get("HMC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -13,20 +13,83 @@
 #include <new>
 #include <vector>
 
+#include "hmc_handle.h"
 #include "hmc_internal.h"
 
 using hmc::DevLattice;
 using hmc::DevState;
+using hmc::Layout;
+
+// ---------------------------------------------------------------------------
+// Launch-event timer
+// ---------------------------------------------------------------------------
+namespace hmc {
+
+hipError_t Timer::flush(hipStream_t s)
+{
+    if (used == 0) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (size_t i = 0; i < used; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+        if (e != hipSuccess) return e;
+        tot.count[kind[i]] += 1;
+        tot.total_ms[kind[i]] += ms;
+    }
+    used = 0;
+    return hipSuccess;
+}
+
+hipError_t Timer::enable(hipStream_t s, bool enable_)
+{
+    if (on) {
+        hipError_t e = flush(s);
+        if (e != hipSuccess) return e;
+    }
+    on = enable_;
+    tot = hmc_timing{};
+    while (on && ev.size() < 2 * kMaxEvents) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        ev.push_back(e);
+    }
+    kind.resize(kMaxEvents);
+    return hipSuccess;
+}
+
+hipError_t Timer::begin(hipStream_t s)
+{
+    if (used == kMaxEvents) {
+        hipError_t e = flush(s);
+        if (e != hipSuccess) return e;
+    }
+    return hipEventRecord(ev[2 * used], s);
+}
+
+hipError_t Timer::end(hipStream_t s, int k)
+{
+    hipError_t e = hipEventRecord(ev[2 * used + 1], s);
+    if (e != hipSuccess) return e;
+    kind[used] = k;
+    used += 1;
+    return hipSuccess;
+}
+
+void Timer::destroy()
+{
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    used = 0;
+    on = false;
+}
+
+}  // namespace hmc
 
 namespace {
 
 constexpr uint32_t kStateMagic = 0x484D4331u;  // "HMC1"
-constexpr size_t kMaxEvents = 16384;           // timing event pairs before a flush
-
-struct Layout {
-    size_t pitch, off_aos, off_nbs, off_state, off_c1, off_part, off_cnt, total;
-    int64_t max_blocks;
-};
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -107,25 +170,6 @@ struct StateHeader {
 
 }  // namespace
 
-struct hmc_lattice {
-    DevLattice d;
-    hmc_params p;
-    hipStream_t stream;
-    Layout lay;
-    int spt = 2, zc = 16;
-    bool m_valid = false;
-    char err[256] = {0};
-    double c1d[181];
-    float c1f[181];
-    DevState init_state;
-    // timing
-    bool timing = false;
-    std::vector<hipEvent_t> ev;      // start/stop pairs
-    std::vector<int> kind;
-    size_t used = 0;
-    hmc_timing tot{};
-};
-
 namespace {
 
 int fail(hmc_lattice* L, int status, const char* what, hipError_t e = hipSuccess)
@@ -137,48 +181,19 @@ int fail(hmc_lattice* L, int status, const char* what, hipError_t e = hipSuccess
     return status;
 }
 
-int flush_timing(hmc_lattice* L)
-{
-    if (L->used == 0) return HMC_OK;
-    hipError_t e = hipStreamSynchronize(L->stream);
-    if (e != hipSuccess) return fail(L, HMC_EHIP, "hipStreamSynchronize", e);
-    for (size_t i = 0; i < L->used; ++i) {
-        float ms = 0.f;
-        e = hipEventElapsedTime(&ms, L->ev[2 * i], L->ev[2 * i + 1]);
-        if (e != hipSuccess) return fail(L, HMC_EHIP, "hipEventElapsedTime", e);
-        L->tot.count[L->kind[i]] += 1;
-        L->tot.total_ms[L->kind[i]] += ms;
-    }
-    L->used = 0;
-    return HMC_OK;
-}
-
 // Runs one launch, bracketed by events on the lattice's stream when timing.
 template <class F>
 int launch(hmc_lattice* L, int kind, const char* what, F f)
 {
-    if (L->timing) {
-        if (L->used == kMaxEvents) {
-            int st = flush_timing(L);
-            if (st != HMC_OK) return st;
-        }
-        while (L->ev.size() < 2 * (L->used + 1)) {
-            hipEvent_t e;
-            hipError_t r = hipEventCreate(&e);
-            if (r != hipSuccess) return fail(L, HMC_EHIP, "hipEventCreate", r);
-            L->ev.push_back(e);
-        }
-        L->kind.resize(L->used + 1);
-        hipError_t r = hipEventRecord(L->ev[2 * L->used], L->stream);
-        if (r != hipSuccess) return fail(L, HMC_EHIP, "hipEventRecord", r);
+    if (L->timer.on) {
+        hipError_t r = L->timer.begin(L->stream);
+        if (r != hipSuccess) return fail(L, HMC_EHIP, "timing event", r);
     }
     hipError_t e = f();
     if (e != hipSuccess) return fail(L, HMC_EHIP, what, e);
-    if (L->timing) {
-        hipError_t r = hipEventRecord(L->ev[2 * L->used + 1], L->stream);
-        if (r != hipSuccess) return fail(L, HMC_EHIP, "hipEventRecord", r);
-        L->kind[L->used] = kind;
-        L->used += 1;
+    if (L->timer.on) {
+        hipError_t r = L->timer.end(L->stream, kind);
+        if (r != hipSuccess) return fail(L, HMC_EHIP, "timing event", r);
     }
     return HMC_OK;
 }
@@ -350,15 +365,21 @@ int hmc_constrained_sweep(hmc_lattice* L, double T, const double eC[3], int32_t 
     return st;
 }
 
-int hmc_observables(hmc_lattice* L, hmc_obs* out)
+}  // extern "C"
+
+namespace hmc {
+
+int enqueue_observables(hmc_lattice* L, DevState* host_dst)
 {
-    if (!L || !out) return HMC_EINVAL;
     int st = measure(L);
     if (st != HMC_OK) return st;
-    DevState s;
-    hipError_t e = hipMemcpyAsync(&s, L->d.st, sizeof(s), hipMemcpyDeviceToHost, L->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    hipError_t e = hipMemcpyAsync(host_dst, L->d.st, sizeof(DevState), hipMemcpyDeviceToHost, L->stream);
     if (e != hipSuccess) return fail(L, HMC_EHIP, "reading the device state", e);
+    return HMC_OK;
+}
+
+int finish_observables(hmc_lattice* L, const DevState& s, hmc_obs* out)
+{
     memset(out, 0, sizeof(*out));
     const double N = (double)L->d.N;
     out->n = L->d.N;
@@ -396,6 +417,21 @@ int hmc_observables(hmc_lattice* L, hmc_obs* out)
         for (int a = 0; a < 3; ++a) out->mean_torque[a] = s.sum_torque[a] / (double)s.torque_samples;
     if (s.nonfinite) return fail(L, HMC_ENUMERIC, "a non-finite value appeared in the reductions");
     return HMC_OK;
+}
+
+}  // namespace hmc
+
+extern "C" {
+
+int hmc_observables(hmc_lattice* L, hmc_obs* out)
+{
+    if (!L || !out) return HMC_EINVAL;
+    DevState s;
+    int st = hmc::enqueue_observables(L, &s);
+    if (st != HMC_OK) return st;
+    hipError_t e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "reading the device state", e);
+    return hmc::finish_observables(L, s, out);
 }
 
 int hmc_reset_stats(hmc_lattice* L)
@@ -565,28 +601,17 @@ int hmc_get_launch(const hmc_lattice* L, int32_t* sites_per_thread, int32_t* z_c
 int hmc_set_timing(hmc_lattice* L, int32_t enable)
 {
     if (!L) return HMC_EINVAL;
-    if (L->timing) {
-        int st = flush_timing(L);
-        if (st != HMC_OK) return st;
-    }
-    L->timing = enable != 0;
-    memset(&L->tot, 0, sizeof(L->tot));
-    // create the events up front so that a timed region does not pay for it
-    while (L->timing && L->ev.size() < 2 * kMaxEvents) {
-        hipEvent_t e;
-        hipError_t r = hipEventCreate(&e);
-        if (r != hipSuccess) return fail(L, HMC_EHIP, "hipEventCreate", r);
-        L->ev.push_back(e);
-    }
+    hipError_t e = L->timer.enable(L->stream, enable != 0);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "switching timing", e);
     return HMC_OK;
 }
 
 int hmc_read_timing(hmc_lattice* L, hmc_timing* out)
 {
     if (!L || !out) return HMC_EINVAL;
-    int st = flush_timing(L);
-    if (st != HMC_OK) return st;
-    *out = L->tot;
+    hipError_t e = L->timer.flush(L->stream);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "reading the timing events", e);
+    *out = L->timer.tot;
     return HMC_OK;
 }
 
@@ -594,7 +619,7 @@ void hmc_destroy(hmc_lattice* L)
 {
     if (!L) return;
     (void)hipStreamSynchronize(L->stream);
-    for (hipEvent_t e : L->ev) (void)hipEventDestroy(e);
+    L->timer.destroy();
     delete L;
 }
 

@@ -95,4 +95,35 @@ size_t pass_lds_bytes(int precision, int hx, int spt);
 // Largest partial count any launch can need.
 int64_t max_blocks_for(int32_t nx, int32_t ny, int32_t nz);
 
+// Batches.  The table of a batch holds one entry per lattice (kernel
+// arguments and launch shape), built on the host by batch_fill_entry.  The
+// lattices of one colour-pass launch share a kernel variant: batch_group
+// names it (sites per thread and halo slots, 9 classes).
+size_t batch_entry_bytes(int precision);
+void batch_fill_entry(void* dst, const DevLattice& d, int spt, int zc);
+int batch_group(const DevLattice& d, int spt);
+// Stores the Boltzmann scale the kernels use for temperature T (float or
+// double by precision) at element i of dst (host memory).
+void batch_store_scale(int precision, double T, void* dst, size_t i);
+constexpr int kBatchGroups = 9;
+
+// One colour-pass launch over the lattices of a group.
+struct BatchLaunch {
+    int group;                 // kernel variant
+    const void* tab;           // device: the batch table
+    const uint32_t* start;     // device: n + 1 work-group offsets
+    const uint32_t* ent;       // device: n table indices
+    uint32_t n;                // lattices in this launch
+    uint32_t nblk;             // start[n]
+    size_t lds;                // dynamic LDS bytes (largest of the group)
+    const void* scale;         // device: per-table-entry scale, float or double
+};
+hipError_t launch_pass_batch(int precision, const BatchLaunch& b, int colour, bool obs, hipStream_t s);
+// Work-group i reduces lattice i's results with flags fin[i] (FinFlags);
+// T[i] is its temperature.
+hipError_t launch_finalize_batch(int precision, const void* tab, uint32_t count, const double* T,
+                                 const int32_t* fin, hipStream_t s);
+// Work-group i clears lattice i's accumulators.
+hipError_t launch_reset_batch(int precision, const void* tab, uint32_t count, hipStream_t s);
+
 }  // namespace hmc

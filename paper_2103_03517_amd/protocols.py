@@ -12,6 +12,11 @@ Eq. 6.
 constraint directions and temperatures and reports the anisotropy energy and
 torque per spin.
 
+``batched_mt`` runs many independent m(T) jobs (one lattice and one
+temperature each, of uneven sizes) as one batch: equilibration, then sampled
+sweeps whose block statistics come from the cumulative accumulators read at
+the block ends (no resets, so the jobs need not be aligned).
+
     python -m paper_2103_03517_amd.protocols mt --precision 32 --size 256
 """
 import argparse
@@ -21,7 +26,7 @@ import sys
 
 import numpy as np
 
-from . import Lattice
+from . import Batch, Lattice
 
 
 def _block_stats(blocks, n, T):
@@ -65,6 +70,99 @@ def mt_sweep(temps, size=256, precision=32, equil=2000, samples=4000, block=200,
                 f"E/N={r['E']:.6f} theta={r['theta_deg']}")
     g.close()
     return out
+
+
+def block_stats_from_reads(reads, n, T):
+    """Block statistics from cumulative observables read at the end of each
+    block: block sums are differences of the running sums (n mean, n (var +
+    mean^2)) between consecutive reads."""
+    blocks = []
+    prev = None
+    for r in reads:
+        ns = r["samples"]
+        m1 = ns * np.asarray(r["mean_m"])
+        m2 = ns * (np.asarray(r["var_m"]) + np.asarray(r["mean_m"]) ** 2)
+        e1 = ns * r["mean_E"]
+        if prev is not None:
+            k = ns - prev[0]
+            mean = (m1 - prev[1]) / k
+            var = (m2 - prev[2]) / k - mean ** 2
+            blocks.append({"mean_m": mean, "var_m": np.maximum(var, 0.0), "mean_E": (e1 - prev[3]) / k})
+        else:
+            blocks.append({"mean_m": m1 / ns, "var_m": np.asarray(r["var_m"]), "mean_E": r["mean_E"]})
+        prev = (ns, m1, m2, e1)
+    return _block_stats(blocks, n, T)
+
+
+def c4_jobs(count=64, seed=4, edges=(48, 64, 80, 96, 128), t_lo=0.05, t_hi=1.7):
+    """The batched workload: cubic edges drawn uniformly from `edges` and
+    temperatures uniform in [t_lo, t_hi), from one seeded generator."""
+    rng = np.random.default_rng(seed)
+    e = rng.choice(np.asarray(edges), size=count)
+    t = rng.uniform(t_lo, t_hi, size=count)
+    return [(int(a), float(b)) for a, b in zip(e, t)]
+
+
+def batched_mt(jobs, precision=32, equil=1000, samples=4000, block=200, seed=4, J=1.0, Ku=0.01,
+               tune=True, trial_sweeps=3, graph=0, timer=None, log=None):
+    """Independent m(T) runs, job i = (edge, T) on an edge^3 periodic lattice
+    started along the easy axis (Philox key `seed`, instance i), advanced
+    together in one batch.  Returns per-job results and the batch timings."""
+    import time
+    import torch
+    lats = [Lattice(e, e, e, precision=precision, J=J, Ku=Ku, eu=(0.0, 0.0, 1.0), seed=seed,
+                    instance=i, init="aligned") for i, (e, _) in enumerate(jobs)]
+    T = [t for _, t in jobs]
+    B = Batch(lats)
+    info = {"tune_s": 0.0}
+    if tune:
+        t0 = time.perf_counter()
+        info["shapes"] = B.tune(T, trial_sweeps)
+        info["tune_s"] = time.perf_counter() - t0
+    if graph:
+        B.set_graph(graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.sweep(T, equil)
+    reads = [[] for _ in jobs]
+    nblk = max(samples // block, 1)
+    for _ in range(nblk):
+        B.sweep(T, block, sample=True)
+        for i, o in enumerate(B.observables()):
+            reads[i].append(o)
+    torch.cuda.synchronize()
+    info["run_s"] = time.perf_counter() - t0
+    out = []
+    for i, (e, t) in enumerate(jobs):
+        r = block_stats_from_reads(reads[i], lats[i].n, t)
+        r.update(edge=e, theta_deg=reads[i][-1]["theta_deg"], sweeps=reads[i][-1]["sweeps_done"])
+        out.append(r)
+    spins = sum(l.n for l in lats)
+    info["updates"] = spins * (equil + nblk * block)
+    info["spins"] = spins
+    if log:
+        log(f"batch of {len(jobs)} jobs, {spins} spins: {info['run_s']:.3f} s, "
+            f"{info['updates'] / info['run_s'] / 1e9:.2f} G updates/s")
+    B.close()
+    for l in lats:
+        l.close()
+    return out, info
+
+
+def compare_precisions(r32, r64):
+    """Per job: |dm| of <|m|> and <m_z> between the FP32 and FP64 runs and the
+    same in units of the combined batch-means standard error."""
+    rows = []
+    for a, b in zip(r32, r64):
+        dm = [abs(a["m"][k] - b["m"][k]) for k in (0, 3)]
+        se = [math.hypot(a["se_m"][k], b["se_m"][k]) for k in (0, 3)]
+        de = abs(a["E"] - b["E"])
+        se_e = math.hypot(a["se_E"], b["se_E"])
+        rows.append({"edge": a["edge"], "T": a["T"], "dm": max(dm),
+                     "dm_over_se": max(d / s if s > 0 else (0.0 if d == 0 else math.inf)
+                                       for d, s in zip(dm, se)),
+                     "dE_over_se": de / se_e if se_e > 0 else 0.0})
+    return rows
 
 
 def ec_of(theta_deg, phi_deg):
@@ -113,6 +211,11 @@ def main(argv=None):
     a.add_argument("--seed", type=int, default=7)
     a.add_argument("--init", default="random", choices=["random", "aligned"])
     a.add_argument("--Ku", type=float, default=0.005)
+    b = sub.add_parser("batched", help="batched independent m(T) jobs, FP32 against FP64")
+    b.add_argument("--count", type=int, default=64)
+    b.add_argument("--equil", type=int, default=1000)
+    b.add_argument("--samples", type=int, default=4000)
+    b.add_argument("--block", type=int, default=200)
     c = sub.add_parser("constrained", help="constrained-direction scan")
     c.add_argument("--size", type=int, default=128)
     c.add_argument("--precision", type=int, default=32)
@@ -129,6 +232,13 @@ def main(argv=None):
         res = mt_sweep(temps, size=args.size, precision=args.precision, equil=args.equil,
                        samples=args.samples, block=args.block, seed=args.seed, init=args.init,
                        Ku=args.Ku, log=log)
+    elif args.cmd == "batched":
+        jobs = c4_jobs(args.count)
+        r32, i32 = batched_mt(jobs, 32, args.equil, args.samples, args.block, log=log)
+        r64, i64 = batched_mt(jobs, 64, args.equil, args.samples, args.block, tune=False, log=log)
+        res = {"fp32": r32, "fp64": r64, "compare": compare_precisions(r32, r64),
+               "info32": {k: v for k, v in i32.items() if k != "shapes"},
+               "info64": {k: v for k, v in i64.items() if k != "shapes"}}
     else:
         res = constrained_scan(list(range(0, 91, 10)), [0, 45], [0.2 * k for k in range(1, 8)],
                                size=args.size, precision=args.precision, sweeps=args.sweeps,

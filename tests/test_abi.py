@@ -83,3 +83,34 @@ def test_null_handles(hmc):
     assert L.hmc_state_bytes(None) == 0
     L.hmc_destroy(None)
     assert L.hmc_last_error(None) == b"no lattice"
+
+
+def test_batch_host_checks(hmc):
+    """Batch entry points: sizes and the argument checks made before any
+    device work."""
+    import ctypes
+    L = hmc.lib()
+    assert L.hmc_batch_workspace_bytes(0) == 0
+    assert L.hmc_batch_workspace_bytes(-3) == 0
+    assert L.hmc_batch_workspace_bytes(65537) == 0
+    sizes = [L.hmc_batch_workspace_bytes(n) for n in (1, 2, 64, 1024, 65536)]
+    assert all(s > 0 and s % 256 == 0 for s in sizes)
+    assert sizes == sorted(sizes)
+    assert sizes[3] < 1024 * 512          # well under 0.5 KB per lattice
+    out = ctypes.c_void_p(123)
+    assert L.hmc_batch_create(None, 1, None, 0, ctypes.byref(out)) == -1
+    assert out.value is None
+    hs = (ctypes.c_void_p * 2)(None, None)
+    assert L.hmc_batch_create(hs, 2, None, 0, ctypes.byref(out)) == -1
+    assert L.hmc_batch_create(hs, 2, None, 0, None) == -1
+    T = (ctypes.c_double * 1)(1.0)
+    assert L.hmc_batch_sweep(None, T, 1, 0) == -1
+    assert L.hmc_batch_tune(None, T, 1) == -1
+    assert L.hmc_batch_set_graph(None, 1) == -1
+    assert L.hmc_batch_set_timing(None, 1) == -1
+    assert L.hmc_batch_read_timing(None, None) == -1
+    assert L.hmc_batch_observables(None, None) == -1
+    assert L.hmc_batch_reset_stats(None) == -1
+    assert L.hmc_batch_sweep_each(None, T, None, 1) == -1
+    L.hmc_batch_destroy(None)
+    assert L.hmc_batch_last_error(None) == b"no batch"

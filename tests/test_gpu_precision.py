@@ -57,3 +57,19 @@ def test_block_statistics_match_the_accumulators(P):
     assert np.allclose(r["m"], whole["mean_m"], rtol=1e-12, atol=1e-14)
     assert np.allclose(r["chi"], whole["chi"], rtol=1e-9, atol=1e-12)
     assert abs(r["E"] - whole["mean_E"]) < 1e-12
+
+
+def test_batched_fp32_jobs_match_fp64(P):
+    """The batched FP32 jobs against the same jobs run as an FP64 batch: every
+    job within 4 combined standard errors (8 jobs x 3 observables), and
+    |dm| <= 1e-3 where the fluctuations allow it (T <= 0.6 at these sizes)."""
+    jobs = [(32, 0.3), (48, 0.5), (32, 0.6), (48, 0.9), (32, 1.2), (48, 1.3), (32, 1.6), (48, 0.1)]
+    kw = dict(equil=500, samples=6000, block=300)
+    r32, _ = P.batched_mt(jobs, 32, tune=False, **kw)
+    r64, _ = P.batched_mt(jobs, 64, tune=False, **kw)
+    for c in P.compare_precisions(r32, r64):
+        print(c, file=sys.stderr, flush=True)
+        assert c["dm_over_se"] <= 4.0, c
+        assert c["dE_over_se"] <= 4.0, c
+        if c["T"] <= 0.6:
+            assert c["dm"] <= 1e-3, c

@@ -1,0 +1,76 @@
+"""The continuous-batching loop (serving.py) on the device.
+
+Each job's result must be the same alone and in a mix (bit for bit: its
+chain depends only on its own key, temperature, sweep schedule and launch
+shape), admission must respect the HBM budget, and a Poisson stream must
+complete with latencies recorded.
+"""
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    from paper_2103_03517_amd import serving
+    assert torch.cuda.is_available()
+    return serving
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _mix(S, seed=5):
+    kw = dict(equil=60, samples=120, block=40, seed=seed)
+    return [S.Job(16, 0.9, instance=0, arrival=0.00, **kw),
+            S.Job(24, 0.4, instance=1, arrival=0.00, **kw),
+            S.Job(32, 1.3, instance=2, arrival=0.02, **kw),
+            S.Job(16, 1.6, instance=3, arrival=0.03, **kw),
+            S.Job(24, 0.2, instance=4, arrival=0.05, **dict(kw, equil=20, samples=200))]
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_result_same_alone_and_in_mix(S, precision):
+    shapes = {16: (1, 4), 24: (2, 8), 32: (1, 16)}
+    mixed = S.Server(precision=precision, quantum=30, shapes=shapes).run(_mix(S))
+    assert len(mixed) == 5
+    for j in mixed:
+        alone_job = [x for x in _mix(S) if x.instance == j.instance][0]
+        alone = S.Server(precision=precision, quantum=7, shapes=shapes).run([alone_job])[0]
+        assert alone.result == j.result, (j.name, alone.result, j.result)
+        assert j.result["sweeps"] == j.total
+    _say("alone == in mix for", [j.name for j in mixed])
+
+
+def test_admission_respects_the_hbm_budget(S):
+    srv0 = S.Server(precision=32)
+    one = srv0.need_bytes(S.Job(24, 1.0))
+    jobs = [S.Job(24, 0.5 + 0.2 * i, equil=20, samples=40, block=20, instance=i) for i in range(3)]
+    srv = S.Server(precision=32, hbm_budget=one + one // 2, quantum=10)
+    done = srv.run(jobs, realtime=False)
+    assert len(done) == 3 and srv.stats["max_active"] == 1
+    assert srv.stats["max_bytes"] <= one + one // 2
+    ref = S.Server(precision=32, quantum=10).run(
+        [S.Job(24, 0.5 + 0.2 * i, equil=20, samples=40, block=20, instance=i) for i in range(3)])
+    for a, b in zip(sorted(done, key=lambda j: j.instance), sorted(ref, key=lambda j: j.instance)):
+        assert a.result == b.result
+    with pytest.raises(ValueError):
+        S.Server(precision=32, hbm_budget=one // 2).run([S.Job(24, 1.0)])
+
+
+def test_poisson_stream_completes_with_latencies(S):
+    jobs = S.poisson_jobs(rate=40.0, seconds=0.5, edges=(16, 24, 32), equil=40, samples=80, block=40)
+    srv = S.Server(precision=32, quantum=20)
+    done = srv.run(jobs)
+    assert len(done) == len(jobs) > 5
+    summ = S.latency_summary(done)
+    _say(summ, srv.stats)
+    assert 0 < summ["p50_s"] <= summ["p99_s"] <= summ["max_s"]
+    for j in done:
+        assert j.arrival <= j.admitted <= j.finished
+        assert j.result["sweeps"] == j.total
+    assert srv.stats["max_active"] >= 2       # requests overlapped on the device
