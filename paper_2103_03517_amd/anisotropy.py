@@ -1,0 +1,105 @@
+"""Temperature dependence of the cubic anisotropy from constrained runs
+(Sec. 2 and Sec. 3 of the paper; Callen-Callen scaling).
+
+With the magnetisation held along e_C(theta, phi), the anisotropy torque per
+spin <tau> (tau = sum_i S_i x (-dE_anis/dS_i)) is the restoring torque of
+the constrained free energy: turning e_C by d(theta) about
+e_phi = (-sin phi, cos phi, 0) costs dF = -<tau> . e_phi d(theta).  So
+
+    F(theta) - F(0) = -integral_0^theta <tau> . e_phi d(theta')
+
+(at T -> 0 this is K_c f(e_C) with f = ex^2 ey^2 + ex^2 ez^2 + ey^2 ez^2,
+which fixes the sign).  K(T) is the amplitude of the cubic angular
+dependence of F, fitted over the scanned directions, and the exponent n of
+K(T)/K(0) = m(T)^n compares with the l(l+1)/2 = 10 of Callen-Callen theory
+for the fourth-order (l = 4) cubic term.  The internal-energy route fits the
+same shape to <E_anis>(theta) instead.
+"""
+import math
+
+import numpy as np
+
+
+def e_c(theta_deg, phi_deg):
+    t, p = math.radians(theta_deg), math.radians(phi_deg)
+    return np.array([math.sin(t) * math.cos(p), math.sin(t) * math.sin(p), math.cos(t)])
+
+
+def e_phi(phi_deg):
+    p = math.radians(phi_deg)
+    return np.array([-math.sin(p), math.cos(p), 0.0])
+
+
+def cubic_f(theta_deg, phi_deg):
+    """f(e_C(theta, phi)) = sin^4 t cos^2 p sin^2 p + sin^2 t cos^2 t."""
+    t, p = np.radians(theta_deg), math.radians(phi_deg)
+    st, ct = np.sin(t), np.cos(t)
+    return st ** 4 * math.cos(p) ** 2 * math.sin(p) ** 2 + st ** 2 * ct ** 2
+
+
+def cubic_torque(theta_deg, phi_deg, Kc):
+    """Torque per spin at T = 0: e x (-Kc grad f(e)) with e = e_C."""
+    e = e_c(theta_deg, phi_deg)
+    g = 2.0 * Kc * np.array([e[0] * (e[1] ** 2 + e[2] ** 2), e[1] * (e[0] ** 2 + e[2] ** 2),
+                             e[2] * (e[0] ** 2 + e[1] ** 2)])
+    return np.cross(e, -g)
+
+
+def free_energy_from_torque(thetas_deg, torques, phi_deg):
+    """F(theta) - F(theta[0]) per spin: trapezoidal integral over theta (in
+    radians) of -<tau> . e_phi."""
+    th = np.radians(np.asarray(thetas_deg, dtype=float))
+    g = -np.asarray(torques, dtype=float) @ e_phi(phi_deg)
+    F = np.zeros_like(th)
+    F[1:] = np.cumsum(0.5 * (g[1:] + g[:-1]) * np.diff(th))
+    return F
+
+
+def fit_cubic_amplitude(curves):
+    """Least-squares K with F(theta) - F(0) = K f(e_C) over all curves, each
+    curve a tuple (thetas_deg, F, phi_deg) starting at theta = 0."""
+    num = den = 0.0
+    for th, F, phi in curves:
+        f = cubic_f(np.asarray(th, dtype=float), phi) - float(cubic_f(0.0, phi))
+        num += float(np.dot(f, F))
+        den += float(np.dot(f, f))
+    return num / den
+
+
+def callen_callen_exponent(K, K0, m):
+    """n of K/K0 = m^n by least squares on the logarithms, through the origin."""
+    x = np.log(np.asarray(m, dtype=float))
+    y = np.log(np.asarray(K, dtype=float) / K0)
+    return float(np.dot(x, y) / np.dot(x, x))
+
+
+def analyse(scan, m_of_T, Kc):
+    """K(T) from the torque and from <E_anis>, and the exponents n.
+
+    scan: rows {theta, phi, T, E_anis, torque} of a constrained scan;
+    m_of_T: {T: <|m|>} from unconstrained runs at the same temperatures."""
+    temps = sorted({r["T"] for r in scan})
+    phis = sorted({r["phi"] for r in scan})
+    out = []
+    for T in temps:
+        curves_tau, curves_e = [], []
+        for phi in phis:
+            rows = sorted((r for r in scan if r["T"] == T and r["phi"] == phi), key=lambda r: r["theta"])
+            th = [r["theta"] for r in rows]
+            if not rows or th[0] != 0:
+                continue
+            F = free_energy_from_torque(th, [r["torque"] for r in rows], phi)
+            E = np.array([r["E_anis"] for r in rows])
+            curves_tau.append((th, F, phi))
+            curves_e.append((th, E - E[0], phi))
+        out.append({"T": T, "K_torque": fit_cubic_amplitude(curves_tau),
+                    "K_energy": fit_cubic_amplitude(curves_e), "m": m_of_T.get(T)})
+    have_m = [r for r in out if r["m"] is not None and r["K_torque"] > 0 and 0 < r["m"] < 1]
+    res = {"Kc": Kc, "rows": out}
+    if len(have_m) >= 2:
+        res["n_torque"] = callen_callen_exponent([r["K_torque"] for r in have_m], Kc, [r["m"] for r in have_m])
+        good_e = [r for r in have_m if r["K_energy"] > 0]
+        if len(good_e) >= 2:
+            res["n_energy"] = callen_callen_exponent([r["K_energy"] for r in good_e], Kc,
+                                                     [r["m"] for r in good_e])
+    return res

@@ -196,6 +196,47 @@ def constrained_scan(thetas, phis, temps, size=128, precision=32, sweeps=3000, e
     return out
 
 
+def unconstrained_m(temps, size=128, precision=32, equil=2000, samples=4000, block=200, seed=3, Kc=0.05,
+                    Ku=0.0, J=1.0):
+    """<|m|> of independent unconstrained chains started along z (an easy
+    axis of the cubic term), one per temperature, run as one batch."""
+    lats = [Lattice(size, size, size, precision=precision, J=J, Kc=Kc, Ku=Ku, seed=seed, instance=1000 + i,
+                    init="aligned") for i in range(len(temps))]
+    B = Batch(lats)
+    B.sweep(temps, equil)
+    reads = [[] for _ in temps]
+    for _ in range(max(samples // block, 1)):
+        B.sweep(temps, block, sample=True)
+        for i, o in enumerate(B.observables()):
+            reads[i].append(o)
+    out = {}
+    for i, T in enumerate(temps):
+        r = block_stats_from_reads(reads[i], lats[i].n, T)
+        out[T] = (r["m"][0], r["se_m"][0])
+    B.close()
+    for l in lats:
+        l.close()
+    return out
+
+
+def anisotropy_run(size=128, precision=32, thetas=tuple(range(0, 91, 10)), phis=(0.0, 45.0),
+                   temps=(0.2, 0.4, 0.6, 0.8, 1.0, 1.2, 1.4), sweeps=3000, equil=1000, Kc=0.05, log=None):
+    """The constrained scan, the unconstrained m(T) at the same temperatures,
+    and K(T) with its Callen-Callen exponent (anisotropy.analyse)."""
+    from . import anisotropy as A
+    scan = constrained_scan(list(thetas), list(phis), list(temps), size=size, precision=precision,
+                            sweeps=sweeps, equil=equil, Kc=Kc, log=log)
+    m = unconstrained_m(list(temps), size=size, precision=precision, Kc=Kc)
+    res = A.analyse(scan, {T: v[0] for T, v in m.items()}, Kc)
+    res["m_se"] = {str(T): v[1] for T, v in m.items()}
+    res["scan"] = scan
+    if log:
+        for r in res["rows"]:
+            log(f"T={r['T']:.2f} m={r['m']:.5f} K_torque={r['K_torque']:.5e} K_energy={r['K_energy']:.5e}")
+        log(f"n (torque) = {res.get('n_torque')}, n (energy) = {res.get('n_energy')}")
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -216,6 +257,10 @@ def main(argv=None):
     b.add_argument("--equil", type=int, default=1000)
     b.add_argument("--samples", type=int, default=4000)
     b.add_argument("--block", type=int, default=200)
+    an = sub.add_parser("anisotropy", help="constrained scan -> K(T) and its m^n scaling")
+    an.add_argument("--size", type=int, default=128)
+    an.add_argument("--sweeps", type=int, default=3000)
+    an.add_argument("--equil", type=int, default=1000)
     c = sub.add_parser("constrained", help="constrained-direction scan")
     c.add_argument("--size", type=int, default=128)
     c.add_argument("--precision", type=int, default=32)
@@ -232,6 +277,8 @@ def main(argv=None):
         res = mt_sweep(temps, size=args.size, precision=args.precision, equil=args.equil,
                        samples=args.samples, block=args.block, seed=args.seed, init=args.init,
                        Ku=args.Ku, log=log)
+    elif args.cmd == "anisotropy":
+        res = anisotropy_run(size=args.size, sweeps=args.sweeps, equil=args.equil, log=log)
     elif args.cmd == "batched":
         jobs = c4_jobs(args.count)
         r32, i32 = batched_mt(jobs, 32, args.equil, args.samples, args.block, log=log)

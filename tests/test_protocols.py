@@ -64,3 +64,54 @@ def test_serving_job_schedule_and_stream():
     gaps = np.diff([0.0] + [x.arrival for x in a])
     assert abs(gaps.mean() - 1 / 20) < 0.015
     assert {x.instance for x in a} == set(range(len(a)))
+
+
+def test_torque_integral_gives_the_cubic_energy():
+    """Synthetic T = 0 torques integrate to Kc f(e_C(theta)) along both scan
+    planes, and the amplitude fit recovers Kc on the 10-degree grid."""
+    from paper_2103_03517_amd import anisotropy as A
+    Kc = 0.05
+    for phi in (0.0, 45.0, 30.0):
+        th = np.arange(0.0, 90.01, 0.5)
+        tau = np.array([A.cubic_torque(t, phi, Kc) for t in th])
+        F = A.free_energy_from_torque(th, tau, phi)
+        ref = Kc * (A.cubic_f(th, phi) - A.cubic_f(0.0, phi))
+        assert np.max(np.abs(F - ref)) < 2e-5 * Kc * 10, phi
+        # the torque is perpendicular to e_C; in the symmetry planes phi = 0
+        # and 45 degrees (df/dphi = 0) it lies along e_phi
+        for t, v in zip(th[::20], tau[::20]):
+            assert abs(np.dot(v, A.e_c(t, phi))) < 1e-15
+            if phi in (0.0, 45.0):
+                assert np.linalg.norm(v - np.dot(v, A.e_phi(phi)) * A.e_phi(phi)) < 1e-12
+    grid = list(range(0, 91, 10))
+    curves = [(grid, A.free_energy_from_torque(grid, [A.cubic_torque(t, p, Kc) for t in grid], p), p)
+              for p in (0.0, 45.0)]
+    assert abs(A.fit_cubic_amplitude(curves) / Kc - 1) < 0.03
+
+
+def test_callen_callen_exponent_recovered():
+    from paper_2103_03517_amd import anisotropy as A
+    m = np.array([0.95, 0.9, 0.8, 0.6])
+    assert abs(A.callen_callen_exponent(0.05 * m ** 10, 0.05, m) - 10.0) < 1e-12
+    assert abs(A.callen_callen_exponent(0.05 * m ** 3, 0.05, m) - 3.0) < 1e-12
+
+
+def test_constrained_reference_torque_integrates_to_free_energy():
+    """End to end on the CPU reference: constrained chains at T -> 0 along a
+    grid of e_C; the integral of their mean torque reproduces Kc f(e_C) -
+    Kc f(z).  Pins the torque sign and the integration together."""
+    from oracle import oracle as O
+    from paper_2103_03517_amd import anisotropy as A
+    Kc, T = 0.05, 0.002
+    th = list(range(0, 91, 5))
+    tau = []
+    for t in th:
+        e = A.e_c(t, 0.0)
+        o = O.OracleLattice(4, 4, 4, J=1.0, Kc=Kc, seed=3, init="aligned", init_dir=tuple(e))
+        o.constrained_sweep(T, tuple(e), 40)
+        o.constrained_sweep(T, tuple(e), 60, sample=True)
+        tau.append(o.observables(T)["mean_torque"])
+    F = A.free_energy_from_torque(th, tau, 0.0)
+    ref = Kc * A.cubic_f(np.array(th, dtype=float), 0.0)
+    assert np.max(np.abs(F - ref)) < 0.03 * Kc / 4, (F, ref)
+    assert abs(F[9] - Kc / 4) < 0.03 * Kc / 4          # theta = 45: the <110> direction
