@@ -180,22 +180,28 @@ def serve_leg(rate=20.0, seconds=10.0):
     800 sweeps each, served by the continuous-batching loop in FP32; then the
     same jobs all at once (saturation) for the capacity in jobs/s."""
     from paper_2103_03517_amd import serving as S
-    jobs = S.poisson_jobs(rate, seconds)
+    jobs = S.poisson_jobs(rate, seconds, wall_fraction=0.2)
     srv = S.Server(precision=32, hbm_budget=32 << 30, quantum=50)
     log(f"leg 6: serving {len(jobs)} m(T) jobs arriving at {rate}/s over {seconds} s")
-    shapes = srv.tune_shapes(sorted({j.edge for j in jobs}))
+    shapes = srv.tune_shapes(sorted({j.shape for j in jobs}))
     done = srv.run(jobs)
     live = S.latency_summary(done)
     log(f"  p50 {live['p50_s'] * 1e3:.1f} ms, p99 {live['p99_s'] * 1e3:.1f} ms, "
         f"max active {srv.stats['max_active']}")
     sat = S.Server(precision=32, hbm_budget=32 << 30, quantum=50, shapes=shapes)
-    done2 = sat.run(S.poisson_jobs(rate, seconds), realtime=False)
+    done2 = sat.run(S.poisson_jobs(rate, seconds, wall_fraction=0.2), realtime=False)
     cap = S.latency_summary(done2)
     log(f"  saturation: {cap['jobs_per_s']:.1f} jobs/s, {cap['updates_per_s'] / 1e9:.1f} G updates/s")
-    return {"workload": f"Poisson arrivals at {rate}/s for {seconds} s (seed 5): m(T) jobs on edge^3 "
+    import numpy as np
+    walls = [j for j in done if j.kind == "wall"]
+    return {"workload": f"Poisson arrivals at {rate}/s for {seconds} s (seed 5): 80% m(T) jobs on edge^3 "
                         "periodic lattices, edge uniform in {32,48,64,96,128,160,192}, T ~ U(0.05, 1.7), "
-                        "Ku=0.01, 200 equilibration + 800 sampled sweeps (blocks of 100), FP32, "
-                        "HBM budget 32 GiB, at most 64 jobs in flight",
+                        "200 equilibration + 800 sampled sweeps (blocks of 100); 20% domain-wall jobs on "
+                        "64x64x512 anti-periodic along z, T ~ U(0.05, 1.2), 1000 + 1000 sweeps, profile "
+                        "fitted every 100; Ku=0.01, FP32, HBM budget 32 GiB, at most 64 jobs in flight",
+            "wall_jobs": len(walls),
+            "wall_p99_latency_s": (float(np.percentile([j.finished - j.arrival for j in walls], 99))
+                                   if walls else None),
             "offered_jobs": len(jobs), "completed": live["jobs"],
             "p50_latency_s": live["p50_s"], "p99_latency_s": live["p99_s"], "max_latency_s": live["max_s"],
             "jobs_per_s": live["jobs_per_s"], "max_active": srv.stats["max_active"],

@@ -3,7 +3,8 @@
  * adaptive Metropolis sweeps of a classical Heisenberg spin lattice
  * (Lepadatu et al., arXiv:2103.03517).
  *
- * The library updates a simple-cubic, fully periodic lattice of unit spins
+ * The library updates a simple-cubic, periodic (optionally anti-periodic
+ * along z) lattice of unit spins
  * with the spin Hamiltonian of Eq. 2 (nearest-neighbour exchange J,
  * uniaxial anisotropy Ku along eu, cubic anisotropy Kc with the Cartesian
  * axes as easy axes for Kc > 0, Zeeman field h), in reduced units: J is
@@ -75,6 +76,10 @@ typedef struct {
     int32_t  init;          /* 0: every spin along init_dir; 1: uniform on the sphere */
     double   init_dir[3];   /* non-zero when init == 0 */
     int32_t  theta0_deg;    /* initial cone angle, 1..180 degrees */
+    int32_t  boundary_z;    /* 0: periodic along z; 1: anti-periodic along z (the
+                               bond between planes nz-1 and 0 couples S_i to -S_j),
+                               which holds one domain wall across z (the domain-wall
+                               method of Sec. 3); x and y stay periodic */
 } hmc_params;
 
 /* Observables.  The instantaneous values describe the spins at the time of
@@ -159,6 +164,12 @@ int hmc_observables(hmc_lattice* L, hmc_obs* out);
 
 /* Clears the accumulators (not the spins, cone angle or sweep counter). */
 int hmc_reset_stats(hmc_lattice* L);
+
+/* Mean spin of every z plane (a slice of nx*ny sites, both colours) of the
+ * current spins: host_out receives 3*nz doubles, plane z at 3z .. 3z+2.  The
+ * magnetisation profile across a wall held by the anti-periodic boundary
+ * (Sec. 3, Eq. 5).  Synchronises.  Errors: HMC_EINVAL, HMC_EHIP. */
+int hmc_plane_means(hmc_lattice* L, double* host_out);
 
 /* Copies the spins between the device and host_xyz, an array of 3*N
  * doubles in AoS order S[3*i + a] with site id i = x + nx*(y + ny*z).

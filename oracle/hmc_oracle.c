@@ -66,6 +66,7 @@ struct oracle_lattice {
     double J, Ku, eu[3], Kc, h[3];
     uint64_t seed;
     uint32_t instance;
+    int32_t apz;        /* 1: anti-periodic along z */
     int32_t theta;
     int64_t sweep;
     int64_t accepted_last;
@@ -184,8 +185,10 @@ int64_t oracle_site_of(const oracle_lattice* L, int32_t colour, int64_t idx)
     return s;
 }
 
-/* Neighbours of site i in the order x-, x+, y-, y+, z-, z+ (periodic). */
-static void neighbours(const oracle_lattice* L, int64_t i, int64_t nb[6])
+/* Neighbours of site i in the order x-, x+, y-, y+, z-, z+ (periodic), and
+ * the sign each one enters the exchange with: -1 for a bond that crosses the
+ * z boundary of an anti-periodic lattice, else +1. */
+static void neighbours(const oracle_lattice* L, int64_t i, int64_t nb[6], double sg[6])
 {
     int64_t x, y, z;
     coords(L, i, &x, &y, &z);
@@ -195,6 +198,11 @@ static void neighbours(const oracle_lattice* L, int64_t i, int64_t nb[6])
     nb[3] = site_id(L, x, (y + 1) % L->ny, z);
     nb[4] = site_id(L, x, y, (z - 1 + L->nz) % L->nz);
     nb[5] = site_id(L, x, y, (z + 1) % L->nz);
+    for (int k = 0; k < 6; ++k) sg[k] = 1.0;
+    if (L->apz) {
+        if (z == 0) sg[4] = -1.0;
+        if (z == L->nz - 1) sg[5] = -1.0;
+    }
 }
 
 static double dot3(const double a[3], const double b[3])
@@ -216,9 +224,10 @@ static double cubic_f(const double s[3])
 double oracle_local_energy(const oracle_lattice* L, int64_t i, const double S[3])
 {
     int64_t nb[6];
-    neighbours(L, i, nb);
+    double sg[6];
+    neighbours(L, i, nb, sg);
     double exch = 0.0;
-    for (int k = 0; k < 6; ++k) exch += dot3(S, &L->S[3 * nb[k]]);
+    for (int k = 0; k < 6; ++k) exch += sg[k] * dot3(S, &L->S[3 * nb[k]]);
     double se = dot3(S, L->eu);
     return -L->J * exch - L->Ku * se * se + L->Kc * cubic_f(S) - dot3(L->h, S);
 }
@@ -231,10 +240,11 @@ static void energy_parts(const oracle_lattice* L, double* e_exch, double* e_uni,
     double ex = 0.0, eu = 0.0, ec = 0.0, ez = 0.0;
     for (int64_t i = 0; i < L->n; ++i) {
         int64_t nb[6];
-        neighbours(L, i, nb);
+        double sg[6];
+        neighbours(L, i, nb, sg);
         const double* s = &L->S[3 * i];
         ex += -L->J * (dot3(s, &L->S[3 * nb[1]]) + dot3(s, &L->S[3 * nb[3]]) +
-                       dot3(s, &L->S[3 * nb[5]]));
+                       sg[5] * dot3(s, &L->S[3 * nb[5]]));
         double se = dot3(s, L->eu);
         eu += -L->Ku * se * se;
         ec += L->Kc * cubic_f(s);
@@ -358,6 +368,11 @@ oracle_lattice* oracle_create(int32_t nx, int32_t ny, int32_t nz,
     L->S = (double*)calloc((size_t)(3 * L->n), sizeof(double));
     if (!L->S) { free(L); return NULL; }
     return L;
+}
+
+void oracle_set_boundary_z(oracle_lattice* L, int32_t antiperiodic)
+{
+    L->apz = antiperiodic ? 1 : 0;
 }
 
 void oracle_destroy(oracle_lattice* L)
@@ -678,10 +693,11 @@ void oracle_heatbath_sweep(oracle_lattice* L, double T, int32_t n_sweeps, int32_
     for (int32_t it = 0; it < n_sweeps; ++it) {
         for (int64_t i = 0; i < L->n; ++i) {
             int64_t nb[6];
-            neighbours(L, i, nb);
+            double sg[6];
+            neighbours(L, i, nb, sg);
             double hl[3] = { L->h[0], L->h[1], L->h[2] };
             for (int k = 0; k < 6; ++k)
-                for (int a = 0; a < 3; ++a) hl[a] += L->J * L->S[3 * nb[k] + a];
+                for (int a = 0; a < 3; ++a) hl[a] += L->J * sg[k] * L->S[3 * nb[k] + a];
             double hn = sqrt(dot3(hl, hl));
             double u[4];
             uint32_t r[4];

@@ -60,6 +60,10 @@ oracle_lattice* oracle_create(int32_t nx, int32_t ny, int32_t nz,
 void    oracle_destroy(oracle_lattice* L);
 
 /* Initial states. */
+/* Boundary along z: 0 periodic (the default), 1 anti-periodic (the bond
+ * between planes nz-1 and 0 enters the exchange with a minus sign; the
+ * domain-wall method of Sec. 3). */
+void    oracle_set_boundary_z(oracle_lattice* L, int32_t antiperiodic);
 void    oracle_init_aligned(oracle_lattice* L, const double dir[3]);
 void    oracle_init_random(oracle_lattice* L);
 void    oracle_set_spins(oracle_lattice* L, const double* S);

@@ -56,6 +56,7 @@ def _load():
                                                          ctypes.c_uint32, ctypes.c_int32]
     lib.oracle_destroy.argtypes = [vp]
     lib.oracle_init_aligned.argtypes = [vp, D3]
+    lib.oracle_set_boundary_z.argtypes = [vp, ctypes.c_int32]
     lib.oracle_init_random.argtypes = [vp]
     lib.oracle_set_spins.argtypes = [vp, D3]
     lib.oracle_get_spins.argtypes = [vp, D3]
@@ -153,7 +154,7 @@ class OracleLattice:
 
     def __init__(self, nx, ny, nz, J=1.0, Ku=0.0, eu=(0.0, 0.0, 1.0), Kc=0.0,
                  h=(0.0, 0.0, 0.0), seed=1, instance=0, theta0_deg=30,
-                 init="aligned", init_dir=(0.0, 0.0, 1.0)):
+                 init="aligned", init_dir=(0.0, 0.0, 1.0), boundary_z="periodic"):
         L = _load()
         self._eu, peu = _d3(eu)
         self._h, ph = _d3(h)
@@ -163,6 +164,8 @@ class OracleLattice:
                                   int(seed), int(instance), int(theta0_deg))
         if not self.h_:
             raise ValueError("invalid oracle lattice parameters")
+        apz = {"periodic": 0, "antiperiodic": 1}[boundary_z] if isinstance(boundary_z, str) else int(boundary_z)
+        L.oracle_set_boundary_z(self.h_, apz)
         if init == "aligned":
             _, pd = _d3(init_dir)
             L.oracle_init_aligned(self.h_, pd)

@@ -29,7 +29,7 @@ class Params(ctypes.Structure):
         ("Kc", ctypes.c_double), ("h", ctypes.c_double * 3),
         ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32),
         ("init", ctypes.c_int32), ("init_dir", ctypes.c_double * 3),
-        ("theta0_deg", ctypes.c_int32),
+        ("theta0_deg", ctypes.c_int32), ("boundary_z", ctypes.c_int32),
     ]
 
 
@@ -56,7 +56,7 @@ TIMING_KINDS = ("pass", "constrained", "reduce", "other")
 
 # every function declared in include/hmc.h
 SYMBOLS = ("hmc_workspace_bytes", "hmc_init_lattice", "hmc_sweep", "hmc_constrained_sweep",
-           "hmc_observables", "hmc_reset_stats", "hmc_copy_spins", "hmc_state_bytes",
+           "hmc_observables", "hmc_reset_stats", "hmc_plane_means", "hmc_copy_spins", "hmc_state_bytes",
            "hmc_get_state", "hmc_set_state", "hmc_set_launch", "hmc_get_launch",
            "hmc_set_timing", "hmc_read_timing", "hmc_destroy", "hmc_strerror",
            "hmc_last_error", "hmc_batch_workspace_bytes", "hmc_batch_create", "hmc_batch_sweep",
@@ -89,6 +89,8 @@ def lib():
     L.hmc_observables.argtypes = [vp, P(Obs)]
     L.hmc_reset_stats.restype = i32
     L.hmc_reset_stats.argtypes = [vp]
+    L.hmc_plane_means.restype = i32
+    L.hmc_plane_means.argtypes = [vp, P(dbl)]
     L.hmc_copy_spins.restype = i32
     L.hmc_copy_spins.argtypes = [vp, P(dbl), i32]
     L.hmc_state_bytes.restype = ctypes.c_size_t
@@ -147,7 +149,7 @@ class HmcError(RuntimeError):
 
 def make_params(nx, ny, nz, precision=64, J=1.0, Ku=0.0, eu=(0.0, 0.0, 1.0), Kc=0.0,
                 h=(0.0, 0.0, 0.0), seed=1, instance=0, init="aligned", init_dir=(0.0, 0.0, 1.0),
-                theta0_deg=30):
+                theta0_deg=30, boundary_z="periodic"):
     p = Params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.precision = int(precision)
@@ -159,6 +161,8 @@ def make_params(nx, ny, nz, precision=64, J=1.0, Ku=0.0, eu=(0.0, 0.0, 1.0), Kc=
     p.init = {"aligned": 0, "random": 1}[init] if isinstance(init, str) else int(init)
     p.init_dir[:] = [float(v) for v in init_dir]
     p.theta0_deg = int(theta0_deg)
+    p.boundary_z = ({"periodic": 0, "antiperiodic": 1}[boundary_z] if isinstance(boundary_z, str)
+                    else int(boundary_z))
     return p
 
 
@@ -233,6 +237,12 @@ class Lattice:
 
     def reset_stats(self):
         self._check(self._lib.hmc_reset_stats(self._h))
+
+    def plane_means(self):
+        """Mean spin of every z plane of the current spins, shape (nz, 3)."""
+        out = np.empty((self.shape[2], 3), dtype=np.float64)
+        self._check(self._lib.hmc_plane_means(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
 
     # -- data movement -----------------------------------------------------
     def spins(self):

@@ -37,6 +37,12 @@ def cubic_f(theta_deg, phi_deg):
     return st ** 4 * math.cos(p) ** 2 * math.sin(p) ** 2 + st ** 2 * ct ** 2
 
 
+def uniaxial_f(theta_deg, phi_deg):
+    """Angular shape of a uniaxial term along z: 1 - cos^2 t = sin^2 t
+    (E_anis = -Ku (S.z)^2 is Ku sin^2 t above its minimum)."""
+    return np.sin(np.radians(theta_deg)) ** 2
+
+
 def cubic_torque(theta_deg, phi_deg, Kc):
     """Torque per spin at T = 0: e x (-Kc grad f(e)) with e = e_C."""
     e = e_c(theta_deg, phi_deg)
@@ -55,12 +61,14 @@ def free_energy_from_torque(thetas_deg, torques, phi_deg):
     return F
 
 
-def fit_cubic_amplitude(curves):
+def fit_cubic_amplitude(curves, shape=None):
     """Least-squares K with F(theta) - F(0) = K f(e_C) over all curves, each
-    curve a tuple (thetas_deg, F, phi_deg) starting at theta = 0."""
+    curve a tuple (thetas_deg, F, phi_deg) starting at theta = 0; f is the
+    cubic shape unless another is given (uniaxial_f)."""
+    shape = shape or cubic_f
     num = den = 0.0
     for th, F, phi in curves:
-        f = cubic_f(np.asarray(th, dtype=float), phi) - float(cubic_f(0.0, phi))
+        f = shape(np.asarray(th, dtype=float), phi) - float(shape(0.0, phi))
         num += float(np.dot(f, F))
         den += float(np.dot(f, f))
     return num / den
@@ -73,11 +81,14 @@ def callen_callen_exponent(K, K0, m):
     return float(np.dot(x, y) / np.dot(x, x))
 
 
-def analyse(scan, m_of_T, Kc):
+def analyse(scan, m_of_T, Kc, kind="cubic"):
     """K(T) from the torque and from <E_anis>, and the exponents n.
 
     scan: rows {theta, phi, T, E_anis, torque} of a constrained scan;
-    m_of_T: {T: <|m|>} from unconstrained runs at the same temperatures."""
+    m_of_T: {T: <|m|>} from unconstrained runs at the same temperatures;
+    kind: "cubic" (Kc f) or "uniaxial" (Ku sin^2 theta about z), Kc being
+    the T = 0 constant of that term."""
+    shape = cubic_f if kind == "cubic" else uniaxial_f
     temps = sorted({r["T"] for r in scan})
     phis = sorted({r["phi"] for r in scan})
     out = []
@@ -92,8 +103,8 @@ def analyse(scan, m_of_T, Kc):
             E = np.array([r["E_anis"] for r in rows])
             curves_tau.append((th, F, phi))
             curves_e.append((th, E - E[0], phi))
-        out.append({"T": T, "K_torque": fit_cubic_amplitude(curves_tau),
-                    "K_energy": fit_cubic_amplitude(curves_e), "m": m_of_T.get(T)})
+        out.append({"T": T, "K_torque": fit_cubic_amplitude(curves_tau, shape),
+                    "K_energy": fit_cubic_amplitude(curves_e, shape), "m": m_of_T.get(T)})
     have_m = [r for r in out if r["m"] is not None and r["K_torque"] > 0 and 0 < r["m"] < 1]
     res = {"Kc": Kc, "rows": out}
     if len(have_m) >= 2:

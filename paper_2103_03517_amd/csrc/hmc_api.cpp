@@ -131,6 +131,10 @@ int validate(const hmc_params* p, char* msg, size_t n)
         snprintf(msg, n, "theta0_deg must be in [1, 180] (got %d)", p->theta0_deg);
         return HMC_EINVAL;
     }
+    if (p->boundary_z != 0 && p->boundary_z != 1) {
+        snprintf(msg, n, "boundary_z must be 0 (periodic) or 1 (anti-periodic)");
+        return HMC_EINVAL;
+    }
     return HMC_OK;
 }
 
@@ -162,7 +166,7 @@ Layout layout_for(const hmc_params* p)
 
 struct StateHeader {
     uint32_t magic, precision;
-    int32_t nx, ny, nz, pad;
+    int32_t nx, ny, nz, boundary_z;
     uint64_t seed;
     uint32_t instance, pad2;
     double J, Ku, eu[3], Kc, h[3];
@@ -276,6 +280,7 @@ int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes, void* h
     d.key1 = (uint32_t)(p->seed >> 32);
     d.instance = p->instance;
     d.init_mode = p->init;
+    d.apz = p->boundary_z;
 
     // 1 - cos(theta) = 2 sin^2(theta/2) for theta = 0..180 degrees
     for (int th = 0; th <= 180; ++th) {
@@ -454,6 +459,19 @@ int hmc_reset_stats(hmc_lattice* L)
     return HMC_OK;
 }
 
+int hmc_plane_means(hmc_lattice* L, double* host_out)
+{
+    if (!L || !host_out) return HMC_EINVAL;
+    // the reduction partials are free between sweeps; nz <= max_blocks
+    int st = launch(L, 2, "plane-mean kernel", [&] { return hmc::launch_plane_means(L->d, L->d.part, L->stream); });
+    if (st != HMC_OK) return st;
+    hipError_t e = hipMemcpyAsync(host_out, L->d.part, 3 * sizeof(double) * (size_t)L->d.nz, hipMemcpyDeviceToHost,
+                                  L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "reading the plane means", e);
+    return HMC_OK;
+}
+
 int hmc_copy_spins(hmc_lattice* L, double* host_xyz, int32_t to_host)
 {
     if (!L || !host_xyz) return HMC_EINVAL;
@@ -525,6 +543,7 @@ static void fill_header(const hmc_lattice* L, StateHeader* h)
     h->nx = L->p.nx;
     h->ny = L->p.ny;
     h->nz = L->p.nz;
+    h->boundary_z = L->p.boundary_z;
     h->seed = L->p.seed;
     h->instance = L->p.instance;
     h->J = L->p.J;

@@ -71,6 +71,7 @@ struct DevLattice {
     uint32_t key0, key1, instance;
     int32_t init_mode;
     double init_dir[3];
+    int32_t apz;              // 1: anti-periodic along z
 };
 
 // Launchers (hmc_kernels.hip).  Each returns the HIP status of the launch;
@@ -84,6 +85,8 @@ enum ConstrainedStep { kAosIn = 0, kNbRed, kPairRed, kNbBlack, kPairBlack, kAosO
 hipError_t launch_constrained(const DevLattice& d, int step, const double eC[3], double T, hipStream_t s,
                               int64_t* blocks);
 hipError_t launch_measure(const DevLattice& d, hipStream_t s, int64_t* blocks);
+// Mean spin of each z plane into out[3*nz] (device memory).
+hipError_t launch_plane_means(const DevLattice& d, double* out, hipStream_t s);
 // Reduces the counts of the colour-0 (red_blocks) and colour-1 (black_blocks)
 // launches and the partials of part_blocks work-groups into the state.
 hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t black_blocks, int64_t part_blocks,

@@ -36,6 +36,7 @@ struct KArgs {
     double* part;
     uint32_t* cnt;       // [2][cnt_stride]
     uint32_t cnt_stride;
+    uint32_t apz;        // 1: anti-periodic along z (the z-wrap bond enters with a minus sign)
 };
 
 template <typename R>
@@ -64,6 +65,7 @@ static KArgs<R> make_args(const DevLattice& d)
     a.part = d.part;
     a.cnt = d.cnt;
     a.cnt_stride = (uint32_t)d.max_blocks;
+    a.apz = (uint32_t)d.apz;
     return a;
 }
 
@@ -103,6 +105,12 @@ template <> struct Gm<double> {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
     }
 };
+
+template <typename R>
+__device__ __forceinline__ V3<R> neg(const V3<R>& v)
+{
+    return V3<R>{-v.x, -v.y, -v.z};
+}
 
 template <typename R>
 struct Arrays {
@@ -457,6 +465,7 @@ struct PassCtx {
     unsigned char* lds[2];
     R c1, scale;
     uint32_t sweep;
+    bool apz;
 };
 
 template <typename R, int C, bool OBS, int SPT, int HALO, int K>
@@ -482,6 +491,14 @@ __device__ __forceinline__ void pass_step(const KArgs<R>& a, const Arrays<R>& g,
 #pragma unroll
         for (int i = 0; i < HALO; ++i)
             if (x.hact[i]) hpp[i] = g.get(O, x.hvoff[i], fpp);
+        // anti-periodic z: plane z + 2 = nz is plane 0 seen across the
+        // boundary; it serves only as the z+1 neighbour of plane nz - 1.
+        // The uniform branch is taken once per tile at most.
+        if (__builtin_expect(x.apz && z + 2u == x.nz, 0)) {
+            __asm__ volatile("");
+#pragma unroll
+            for (int j = 0; j < SPT; ++j) opp[j] = neg(opp[j]);
+        }
     }
     const unsigned char* L = x.lds[B];
     const uint32_t fz = plane_off(z);
@@ -538,6 +555,7 @@ __device__ __forceinline__ void pass_tile(const KArgs<R>& a, const uint32_t zc, 
     x.c1 = a.c1tab[a.st->theta];
     x.sweep = (uint32_t)a.st->sweep;
     x.scale = scale;
+    x.apz = a.apz != 0;
 
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
@@ -588,6 +606,16 @@ __device__ __forceinline__ void pass_tile(const KArgs<R>& a, const uint32_t zc, 
             }
 #pragma unroll
         for (int j = 0; j < SPT; ++j) LdsPlane<R>::put(x.lds[0], x.W, x.w[j], rB[j]);
+        // anti-periodic z: the z-1 plane of z0 = 0 and the z+1 plane of
+        // z0 = nz - 1 lie across the boundary (both used only as z neighbours)
+        if (x.apz && x.z0 == 0) {
+#pragma unroll
+            for (int j = 0; j < SPT; ++j) rA[j] = neg(rA[j]);
+        }
+        if (x.apz && x.z0 + 1u == a.nz) {
+#pragma unroll
+            for (int j = 0; j < SPT; ++j) rC[j] = neg(rC[j]);
+        }
     }
     __syncthreads();
 
@@ -666,7 +694,11 @@ __device__ __forceinline__ void gather_neighbours(const KArgs<R>& a, const Array
     const uint32_t zp = inpl + P * (z == nz - 1 ? 0 : z + 1);
     const V3<R> same = g.get(O, k * rs, 0), xd = g.get(O, d * rs, 0);
     const V3<R> vym = g.get(O, ym * rs, 0), vyp = g.get(O, yp * rs, 0);
-    const V3<R> vzm = g.get(O, zm * rs, 0), vzp = g.get(O, zp * rs, 0);
+    V3<R> vzm = g.get(O, zm * rs, 0), vzp = g.get(O, zp * rs, 0);
+    if (a.apz) {
+        if (z == 0) vzm = neg(vzm);
+        if (z == nz - 1) vzp = neg(vzp);
+    }
     const V3<R> xm = p ? same : xd;
     const V3<R> xp = p ? xd : same;
     nb = V3<R>{((((xm.x + xp.x) + vym.x) + vyp.x) + vzm.x) + vzp.x,
@@ -730,7 +762,7 @@ __global__ __launch_bounds__(kThreads) void aos_copy_kernel(const KArgs<R> a, Ve
 // colour C, in the order x-, x+, y-, y+, z-, z+.
 template <int C>
 __device__ __forceinline__ void neighbour_indices(uint32_t k, uint32_t hx, uint32_t ny, uint32_t nz, uint32_t P,
-                                                  uint32_t (&nb)[6])
+                                                  uint32_t (&nb)[6], bool& zm_wraps, bool& zp_wraps)
 {
     const uint32_t kx = k % hx, r = k / hx;
     const uint32_t y = r % ny, z = r / ny;
@@ -744,6 +776,8 @@ __device__ __forceinline__ void neighbour_indices(uint32_t k, uint32_t hx, uint3
     nb[3] = kx + hx * (y == ny - 1 ? 0 : y + 1) + fz;
     nb[4] = inpl + P * (z == 0 ? nz - 1 : z - 1);
     nb[5] = inpl + P * (z == nz - 1 ? 0 : z + 1);
+    zm_wraps = z == 0;
+    zp_wraps = z == nz - 1;
 }
 
 // Neighbour sums of colour C (from the AoS copy of the other colour).  With
@@ -758,10 +792,15 @@ __global__ __launch_bounds__(kThreads) void nbsum_kernel(const KArgs<R> a, const
     Acc acc;
     if (k < a.Nc) {
         uint32_t id[6];
-        neighbour_indices<C>(k, a.hx, a.ny, a.nz, a.P, id);
+        bool wm, wp;
+        neighbour_indices<C>(k, a.hx, a.ny, a.nz, a.P, id, wm, wp);
         V3<R> v[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) v[i] = ld4<R>(other, id[i]);
+        if (a.apz) {
+            if (wm) v[4] = neg(v[4]);
+            if (wp) v[5] = neg(v[5]);
+        }
         const V3<R> nb{((((v[0].x + v[1].x) + v[2].x) + v[3].x) + v[4].x) + v[5].x,
                        ((((v[0].y + v[1].y) + v[2].y) + v[3].y) + v[4].y) + v[5].y,
                        ((((v[0].z + v[1].z) + v[2].z) + v[3].z) + v[4].z) + v[5].z};
@@ -870,6 +909,30 @@ __global__ __launch_bounds__(kThreads) void measure_kernel(const KArgs<R> a)
         add_site<R, true>(acc, a.m, red);
     }
     block_end<R, true>(a, 1, blockIdx.x, 0u, acc, scratch);
+}
+
+// Mean spin of every z plane (both colours), for wall profiles: work-group z
+// sums the 2P spins of plane z in a fixed order and writes the mean to
+// out[3z .. 3z+2].
+template <typename R>
+__global__ __launch_bounds__(kThreads) void plane_mean_kernel(const KArgs<R> a, double* out)
+{
+    __shared__ double scratch[5 * 3];
+    const Arrays<R> g(a);
+    const uint32_t z = blockIdx.x;
+    const uint32_t off = a.P * (uint32_t)sizeof(R) * z;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (uint32_t q = threadIdx.x; q < a.P; q += kThreads) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const V3<R> s = g.get(c, q * (uint32_t)sizeof(R), off);
+            v[0] += (double)s.x;
+            v[1] += (double)s.y;
+            v[2] += (double)s.z;
+        }
+    }
+    block_sum<3>(v, scratch);
+    if (threadIdx.x < 3) out[3 * (size_t)z + threadIdx.x] = scratch[threadIdx.x] / (2.0 * (double)a.P);
 }
 
 // ---------------------------------------------------------------------------
@@ -999,6 +1062,13 @@ hipError_t launch_constrained(const DevLattice& d, int step, const double eC[3],
 {
     if (d.precision == 32) constrained_go<float>(d, step, eC, T, s, blocks);
     else constrained_go<double>(d, step, eC, T, s, blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_means(const DevLattice& d, double* out, hipStream_t s)
+{
+    if (d.precision == 32) plane_mean_kernel<float><<<d.nz, kThreads, 0, s>>>(make_args<float>(d), out);
+    else plane_mean_kernel<double><<<d.nz, kThreads, 0, s>>>(make_args<double>(d), out);
     return hipGetLastError();
 }
 

@@ -237,6 +237,96 @@ def anisotropy_run(size=128, precision=32, thetas=tuple(range(0, 91, 10)), phis=
     return res
 
 
+def uniaxial_K(temps, size=64, precision=32, thetas=(0, 30, 60, 90), Ku=0.01, J=1.0, sweeps=3000, equil=1000,
+               seed=8):
+    """K(T) of a uniaxial term along z from constrained runs at a few angles
+    (torque route, anisotropy.analyse with the sin^2 shape)."""
+    from . import anisotropy as A
+    scan = []
+    run = 0
+    for T in temps:
+        for th in thetas:
+            ec = ec_of(th, 0.0)
+            g = Lattice(size, size, size, precision=precision, J=J, Ku=Ku, eu=(0.0, 0.0, 1.0), seed=seed,
+                        instance=run, init="aligned", init_dir=ec)
+            g.constrained_sweep(T, ec, equil)
+            g.constrained_sweep(T, ec, sweeps - equil, sample=True)
+            o = g.observables()
+            g.close()
+            scan.append({"theta": th, "phi": 0.0, "T": T, "E_anis": o["mean_Eanis"], "torque": o["mean_torque"]})
+            run += 1
+    res = A.analyse(scan, {}, Ku, kind="uniaxial")
+    return {r["T"]: r["K_torque"] for r in res["rows"]}
+
+
+def wall_run(temps, shape=(64, 64, 512), precision=32, J=1.0, Ku=0.01, equil=2000, samples=4000, every=100,
+             seed=6, K_of_T=None, log=None):
+    """Domain-wall width across temperatures (Sec. 3, Eq. 5): one lattice per
+    temperature, anti-periodic along z and started from a sharp wall, all in
+    one batch; the plane profile of m_z is fitted every `every` sampled
+    sweeps and the widths averaged.  With K_of_T, A(T) = K Delta^2/pi^2."""
+    from . import walls as Wm
+    nx, ny, nz = shape
+    lats = []
+    for i, T in enumerate(temps):
+        g = Lattice(nx, ny, nz, precision=precision, J=J, Ku=Ku, eu=(0.0, 0.0, 1.0), seed=seed, instance=i,
+                    init="aligned", boundary_z="antiperiodic")
+        g.set_spins(Wm.initial_wall(nx, ny, nz))
+        lats.append(g)
+    B = Batch(lats)
+    B.sweep(list(temps), equil)
+    fits = [[] for _ in temps]
+    for _ in range(max(samples // every, 1)):
+        B.sweep(list(temps), every, sample=True)
+        for i, g in enumerate(lats):
+            prof = g.plane_means()[:, 2]
+            try:
+                fits[i].append(Wm.fit_wall(prof, delta_guess=Wm.zero_temperature_width(J, Ku)))
+            except RuntimeError:
+                pass
+    obs = B.observables()
+    out = []
+    for i, T in enumerate(temps):
+        f = np.array(fits[i]) if fits[i] else np.zeros((0, 3))
+        r = {"T": T, "fits": len(f), "mean_E": obs[i]["mean_E"]}
+        if len(f):
+            r.update(m_wall=float(f[:, 0].mean()), delta=float(f[:, 2].mean()),
+                     se_delta=float(f[:, 2].std(ddof=1) / math.sqrt(len(f))) if len(f) > 1 else float("nan"))
+            if K_of_T is not None and T in K_of_T:
+                r["K"] = K_of_T[T]
+                r["A"] = Wm.exchange_stiffness(K_of_T[T], r["delta"])
+        out.append(r)
+        if log:
+            log(f"T={T:.3f} wall fits {r['fits']}: Delta={r.get('delta', float('nan')):.3f} "
+                f"m={r.get('m_wall', float('nan')):.4f} A={r.get('A', float('nan'))}")
+    B.close()
+    for g in lats:
+        g.close()
+    return out
+
+
+def stiffness_run(temps=(0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.2), Ku=0.01, J=1.0,
+                  shape=(64, 64, 512), log=None):
+    """Exchange stiffness A(T) = K(T) Delta(T)^2 / pi^2 with K(T) from
+    constrained runs and m(T) from unconstrained runs, and the exponent k of
+    A(T)/A(0) = m^k (A(0) = J/2) over the low-temperature points (m > 0.6)."""
+    from . import anisotropy as A
+    K = uniaxial_K(list(temps), Ku=Ku, J=J)
+    walls = wall_run(list(temps), shape=shape, Ku=Ku, J=J, K_of_T=K, log=log)
+    m = unconstrained_m(list(temps), size=64, Kc=0.0, Ku=Ku, J=J)
+    rows = []
+    for w in walls:
+        w["m"] = m[w["T"]][0]
+        rows.append(w)
+    low = [r for r in rows if "A" in r and r["m"] > 0.6 and r["A"] > 0]
+    res = {"rows": rows, "A0": J / 2.0}
+    if len(low) >= 2:
+        res["k"] = A.callen_callen_exponent([r["A"] for r in low], J / 2.0, [r["m"] for r in low])
+    if log:
+        log(f"A(T) ~ m^k: k = {res.get('k')}")
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -261,6 +351,9 @@ def main(argv=None):
     an.add_argument("--size", type=int, default=128)
     an.add_argument("--sweeps", type=int, default=3000)
     an.add_argument("--equil", type=int, default=1000)
+    w = sub.add_parser("stiffness", help="domain-wall widths -> exchange stiffness A(T)")
+    w.add_argument("--nz", type=int, default=512)
+    w.add_argument("--cross", type=int, default=64)
     c = sub.add_parser("constrained", help="constrained-direction scan")
     c.add_argument("--size", type=int, default=128)
     c.add_argument("--precision", type=int, default=32)
@@ -277,6 +370,8 @@ def main(argv=None):
         res = mt_sweep(temps, size=args.size, precision=args.precision, equil=args.equil,
                        samples=args.samples, block=args.block, seed=args.seed, init=args.init,
                        Ku=args.Ku, log=log)
+    elif args.cmd == "stiffness":
+        res = stiffness_run(shape=(args.cross, args.cross, args.nz), log=log)
     elif args.cmd == "anisotropy":
         res = anisotropy_run(size=args.size, sweeps=args.sweeps, equil=args.equil, log=log)
     elif args.cmd == "batched":

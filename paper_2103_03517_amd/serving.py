@@ -1,7 +1,9 @@
-"""Continuous batching of m(T) jobs on one device.
+"""Continuous batching of m(T) and domain-wall jobs on one device.
 
-Requests (one lattice size, one temperature, a sweep budget each) arrive over
-time.  The loop admits waiting requests in arrival order whenever a slot is
+Requests (one lattice, one temperature, a sweep budget each) arrive over
+time.  An m(T) job runs a periodic cube and reports <|m|>, chi and E with
+batch-means errors; a wall job runs a lattice that is anti-periodic along z
+from a sharp wall and reports the fitted wall width (Sec. 3, Eq. 5).  The loop admits waiting requests in arrival order whenever a slot is
 free and their workspace fits in the HBM budget, advances every admitted job
 together through the batch interface (one launch per colour pass for all of
 them, each job with its own temperature and its own sample flag), reads the
@@ -26,16 +28,26 @@ import torch
 
 from . import Batch, Lattice, workspace_bytes, make_params
 from .protocols import block_stats_from_reads
+from . import walls as W
 
 
 class Job:
-    """One m(T) request: `equil` unsampled sweeps, then `samples` sampled
-    sweeps read every `block` sweeps."""
+    """One request: `equil` unsampled sweeps, then `samples` sampled sweeps
+    read every `block` sweeps.  kind "mt": an edge^3 periodic cube started
+    along z; kind "wall": a shape = (nx, ny, nz) lattice anti-periodic along
+    z, started from a sharp wall, whose m_z plane profile is kept at every
+    block end and fitted when the job retires."""
 
     def __init__(self, edge, T, equil=200, samples=800, block=100, seed=5, instance=0, Ku=0.01,
-                 J=1.0, arrival=0.0, name=None):
+                 J=1.0, arrival=0.0, name=None, kind="mt", shape=None):
         if samples % block or equil < 0 or samples <= 0 or block <= 0:
             raise ValueError("samples must be a positive multiple of block")
+        if kind not in ("mt", "wall"):
+            raise ValueError(f"unknown job kind {kind}")
+        self.kind = kind
+        self.shape = tuple(int(v) for v in shape) if shape is not None else (int(edge),) * 3
+        self.n = self.shape[0] * self.shape[1] * self.shape[2]
+        self.profiles = []
         self.edge, self.T = int(edge), float(T)
         self.equil, self.samples, self.block = int(equil), int(samples), int(block)
         self.seed, self.instance, self.Ku, self.J = int(seed), int(instance), float(Ku), float(J)
@@ -52,8 +64,9 @@ class Job:
         return self.equil + self.samples
 
     def params(self, precision):
-        return make_params(self.edge, self.edge, self.edge, precision=precision, J=self.J, Ku=self.Ku,
-                           eu=(0.0, 0.0, 1.0), seed=self.seed, instance=self.instance, init="aligned")
+        return make_params(*self.shape, precision=precision, J=self.J, Ku=self.Ku, eu=(0.0, 0.0, 1.0),
+                           seed=self.seed, instance=self.instance, init="aligned",
+                           boundary_z="antiperiodic" if self.kind == "wall" else "periodic")
 
     def sampling(self):
         return self.done >= self.equil
@@ -67,17 +80,28 @@ class Job:
 
 
 def poisson_jobs(rate=20.0, seconds=10.0, seed=5, edges=(32, 48, 64, 96, 128, 160, 192),
-                 t_lo=0.05, t_hi=1.7, **job_kw):
-    """Poisson arrivals of m(T) jobs: exponential gaps of mean 1/rate, edges
-    uniform over `edges`, temperatures uniform in [t_lo, t_hi)."""
+                 t_lo=0.05, t_hi=1.7, wall_fraction=0.0, wall_shape=(64, 64, 512), wall_t_hi=1.2,
+                 wall_sweeps=(1000, 1000, 100), **job_kw):
+    """Poisson arrivals: exponential gaps of mean 1/rate.  With probability
+    wall_fraction a job is a wall job on wall_shape at T ~ U(t_lo,
+    wall_t_hi) with (equil, samples, block) = wall_sweeps; otherwise an m(T)
+    job with the edge uniform over `edges` and T ~ U(t_lo, t_hi)."""
     rng = np.random.default_rng(seed)
     jobs, t, i = [], 0.0, 0
     while True:
         t += rng.exponential(1.0 / rate)
         if t >= seconds:
             break
-        jobs.append(Job(int(rng.choice(edges)), float(rng.uniform(t_lo, t_hi)), seed=seed, instance=i,
-                        arrival=t, **job_kw))
+        edge = int(rng.choice(edges))
+        T = float(rng.uniform(t_lo, t_hi))
+        if rng.uniform() < wall_fraction:
+            eq, smp, blk = wall_sweeps
+            T = t_lo + (T - t_lo) * (wall_t_hi - t_lo) / (t_hi - t_lo)
+            jobs.append(Job(edge, T, equil=eq, samples=smp, block=blk, seed=seed, instance=i, arrival=t,
+                            kind="wall", shape=wall_shape,
+                            **{k: v for k, v in job_kw.items() if k not in ("equil", "samples", "block")}))
+        else:
+            jobs.append(Job(edge, T, seed=seed, instance=i, arrival=t, **job_kw))
         i += 1
     return jobs
 
@@ -101,32 +125,44 @@ class Server:
     def need_bytes(self, job):
         return workspace_bytes(job.params(self.precision))
 
-    def tune_shapes(self, edges, T=1.0, trial_sweeps=3):
-        """One lattice per edge, tuned together in one batch."""
-        lats = [Lattice(e, e, e, precision=self.precision, Ku=0.01, seed=1, instance=i)
-                for i, e in enumerate(edges)]
+    def tune_shapes(self, shapes, T=1.0, trial_sweeps=3):
+        """One lattice per shape (nx, ny, nz), tuned together in one batch;
+        the launch shapes are kept per lattice shape."""
+        shapes = [tuple(s) for s in shapes]
+        lats = [Lattice(*s, precision=self.precision, Ku=0.01, seed=1, instance=i) for i, s in enumerate(shapes)]
         B = Batch(lats)
-        shapes = B.tune([T] * len(lats), trial_sweeps)
+        launch = B.tune([T] * len(lats), trial_sweeps)
         B.close()
         for l in lats:
             l.close()
-        self.shapes.update({int(e): tuple(s) for e, s in zip(edges, shapes)})
+        self.shapes.update({s: tuple(ln) for s, ln in zip(shapes, launch)})
         return dict(self.shapes)
 
     def _admit(self, job, now):
-        p = job.params(self.precision)
-        job.lattice = Lattice(job.edge, job.edge, job.edge, precision=self.precision, J=job.J, Ku=job.Ku,
-                              eu=(0.0, 0.0, 1.0), seed=job.seed, instance=job.instance, init="aligned")
-        assert job.lattice.params.seed == p.seed
-        if job.edge in self.shapes:
-            job.lattice.set_launch(*self.shapes[job.edge])
+        job.lattice = Lattice(*job.shape, precision=self.precision, J=job.J, Ku=job.Ku, eu=(0.0, 0.0, 1.0),
+                              seed=job.seed, instance=job.instance, init="aligned",
+                              boundary_z="antiperiodic" if job.kind == "wall" else "periodic")
+        if job.kind == "wall":
+            job.lattice.set_spins(W.initial_wall(*job.shape))
+        if job.shape in self.shapes:
+            job.lattice.set_launch(*self.shapes[job.shape])
         job.admitted = now
         job.bytes = self.need_bytes(job)
 
     def _retire(self, job, now):
         job.result = block_stats_from_reads(job.reads, job.lattice.n, job.T)
-        job.result.update(edge=job.edge, sweeps=job.reads[-1]["sweeps_done"],
-                          theta_deg=job.reads[-1]["theta_deg"])
+        job.result.update(edge=job.edge, shape=list(job.shape), kind=job.kind,
+                          sweeps=job.reads[-1]["sweeps_done"], theta_deg=job.reads[-1]["theta_deg"])
+        if job.kind == "wall":
+            fits = []
+            for prof in job.profiles:
+                try:
+                    fits.append(W.fit_wall(prof, delta_guess=W.zero_temperature_width(job.J, job.Ku)))
+                except RuntimeError:
+                    pass
+            if fits:
+                f = np.array(fits)
+                job.result.update(delta=float(f[:, 2].mean()), m_wall=float(f[:, 0].mean()), wall_fits=len(f))
         job.finished = now
         job.lattice.close()
         job.lattice = None
@@ -191,6 +227,8 @@ class Server:
                 for j, o, hit in zip(active, obs, at_block_end):
                     if hit:
                         j.reads.append(o)
+                        if j.kind == "wall":
+                            j.profiles.append(j.lattice.plane_means()[:, 2])
             finished = [j for j in active if j.done >= j.total]
             if finished:
                 now = clock()
@@ -212,7 +250,7 @@ class Server:
 def latency_summary(done, window=None):
     lat = np.array([j.finished - j.arrival for j in done])
     span = window if window is not None else max(j.finished for j in done)
-    updates = sum(j.edge ** 3 * j.total for j in done)
+    updates = sum(j.n * j.total for j in done)
     return {"jobs": len(done), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "mean_s": float(lat.mean()), "max_s": float(lat.max()), "span_s": float(span),
             "jobs_per_s": len(done) / span, "updates_per_s": updates / span}
@@ -235,7 +273,7 @@ def main(argv=None):
     srv = Server(precision=args.precision, hbm_budget=int(args.budget_gib * (1 << 30)), quantum=args.quantum,
                  log=log)
     if not args.no_tune:
-        log(f"tuned shapes: {srv.tune_shapes(sorted({j.edge for j in jobs}))}")
+        log(f"tuned shapes: {srv.tune_shapes(sorted({j.shape for j in jobs}))}")
     done = srv.run(jobs)
     out = latency_summary(done)
     out.update(offered_jobs=len(jobs), rate=args.rate, stats=srv.stats)

@@ -44,7 +44,8 @@ def test_strerror(hmc):
     (dict(nx=3), -2), (dict(ny=0), -2), (dict(nz=5), -2), (dict(nx=2048), -2),
     (dict(precision=16), -1), (dict(J=float("nan")), -1), (dict(eu=(0, 0, 0)), -1),
     (dict(h=(0, float("inf"), 0)), -1), (dict(theta0_deg=0), -1), (dict(theta0_deg=181), -1),
-    (dict(init=2), -1), (dict(init_dir=(0, 0, 0)), -1),
+    (dict(init=2), -1), (dict(init_dir=(0, 0, 0)), -1), (dict(boundary_z=2), -1),
+    (dict(boundary_z=-1), -1),
 ])
 def test_validation(hmc, kw, status):
     base = dict(nx=4, ny=4, nz=4)
@@ -80,6 +81,7 @@ def test_null_handles(hmc):
     L = hmc.lib()
     assert L.hmc_sweep(None, 1.0, 1, 0) == -1
     assert L.hmc_observables(None, None) == -1
+    assert L.hmc_plane_means(None, None) == -1
     assert L.hmc_state_bytes(None) == 0
     L.hmc_destroy(None)
     assert L.hmc_last_error(None) == b"no lattice"

@@ -142,6 +142,55 @@ def test_constrained_sweep_fp64_matches_reference(H, O, shape):
     assert abs(a["mean_Eanis"] - b["mean_Eanis"]) < 1e-12
 
 
+# (shape, sites per thread, z chunk): z chunks that put a tile start on the
+# last plane (rC across the boundary), end a tile's march on it (the z+2 load
+# across the boundary) and start on plane 0 (the z-1 plane across it)
+APSHAPES = [((4, 4, 4), 2, 16), ((6, 10, 4), 1, 3), ((8, 8, 2), 1, 1), ((4, 4, 12), 4, 2),
+            ((34, 6, 4), 2, 1), ((8, 6, 10), 1, 4)]
+
+
+@pytest.mark.parametrize("shape,spt,zc", APSHAPES)
+def test_antiperiodic_z_fp64_matches_reference(H, O, shape, spt, zc):
+    _say("antiperiodic fp64", shape, spt, zc)
+    kw = dict(inputs.random_params(5 * sum(shape)), seed=99 + shape[2], instance=4, theta0_deg=35,
+              boundary_z="antiperiodic")
+    n = shape[0] * shape[1] * shape[2]
+    S = inputs.random_unit_spins(n, 321)
+    g, o = _pair(H, O, shape, kw, spins=S)
+    g.set_launch(spt, zc)
+    T = 0.8
+
+    def step(s):
+        g.sweep(T, sample=(s % 3 == 0))
+        return o.sweep(T, sample=(s % 3 == 0))
+
+    _compare_every_sweep(g, o, 60, step, shape)
+    a, b = g.observables(), o.observables(T)
+    for k in ("E", "E_exch"):
+        assert abs(a[k] - b[k]) <= 1e-11 * max(1.0, abs(b[k])), k
+    assert np.allclose(a["mean_E"], b["mean_E"], rtol=1e-11, atol=1e-13)
+    # constrained sweeps on the same lattice
+    eC = np.array([0.3, -0.4, 0.866])
+    eC /= np.linalg.norm(eC)
+    for _ in range(10):
+        g.constrained_sweep(T, eC, sample=True)
+        o.constrained_sweep(T, eC, sample=True)
+        assert np.max(np.abs(g.spins() - o.spins())) <= TOL
+    assert g.observables()["theta_deg"] == o.counters()[0]
+
+
+def test_plane_means(H):
+    """Mean spin per z plane equals the average of the spins of that plane."""
+    shape = (10, 6, 8)
+    g = H.Lattice(*shape, precision=64, init="random", seed=3, boundary_z="antiperiodic")
+    g.sweep(0.7, 5)
+    S = g.spins().reshape(shape[2], shape[1], shape[0], 3)
+    assert np.allclose(g.plane_means(), S.mean(axis=(1, 2)), rtol=0, atol=1e-14)
+    h = H.Lattice(*shape, precision=32, init="random", seed=3)
+    S = h.spins().reshape(shape[2], shape[1], shape[0], 3)
+    assert np.allclose(h.plane_means(), S.mean(axis=(1, 2)), rtol=0, atol=1e-12)
+
+
 def test_mixed_standard_and_constrained(H, O):
     """Standard and constrained sweeps share the sweep counter and cone angle;
     the constrained pass takes M_L from the current spins after a standard one."""

@@ -30,14 +30,16 @@ def _mix(S, seed=5):
             S.Job(24, 0.4, instance=1, arrival=0.00, **kw),
             S.Job(32, 1.3, instance=2, arrival=0.02, **kw),
             S.Job(16, 1.6, instance=3, arrival=0.03, **kw),
-            S.Job(24, 0.2, instance=4, arrival=0.05, **dict(kw, equil=20, samples=200))]
+            S.Job(24, 0.2, instance=4, arrival=0.05, **dict(kw, equil=20, samples=200)),
+            S.Job(0, 0.3, instance=5, arrival=0.01, kind="wall", shape=(8, 8, 64), Ku=0.05, seed=seed,
+                  equil=100, samples=160, block=40)]
 
 
 @pytest.mark.parametrize("precision", [32, 64])
 def test_result_same_alone_and_in_mix(S, precision):
-    shapes = {16: (1, 4), 24: (2, 8), 32: (1, 16)}
+    shapes = {(16,) * 3: (1, 4), (24,) * 3: (2, 8), (32,) * 3: (1, 16)}
     mixed = S.Server(precision=precision, quantum=30, shapes=shapes).run(_mix(S))
-    assert len(mixed) == 5
+    assert len(mixed) == 6
     for j in mixed:
         alone_job = [x for x in _mix(S) if x.instance == j.instance][0]
         alone = S.Server(precision=precision, quantum=7, shapes=shapes).run([alone_job])[0]
@@ -74,3 +76,17 @@ def test_poisson_stream_completes_with_latencies(S):
         assert j.arrival <= j.admitted <= j.finished
         assert j.result["sweeps"] == j.total
     assert srv.stats["max_active"] >= 2       # requests overlapped on the device
+
+
+def test_wall_job_width_at_low_temperature(S):
+    """A wall job at T = 0.05 (Ku = 0.05, 16x16x128 anti-periodic along z)
+    reports the width pi sqrt(J/(2 Ku)) of the continuum wall within 6%."""
+    from paper_2103_03517_amd import walls as W
+    job = S.Job(0, 0.05, kind="wall", shape=(16, 16, 128), Ku=0.05, equil=1500, samples=1000, block=100)
+    done = S.Server(precision=32, quantum=100).run([job])
+    r = done[0].result
+    d0 = W.zero_temperature_width(1.0, 0.05)
+    _say("wall width", r["delta"], "continuum", d0, "fits", r["wall_fits"])
+    assert r["wall_fits"] == 10
+    assert abs(r["delta"] / d0 - 1) < 0.06
+    assert r["m_wall"] > 0.95

@@ -177,6 +177,51 @@ def test_aligned_state_energies(oracle_mod):
     assert abs(L.total_energy() / L.n - (-3.0 + 0.05 / 3 - h @ d)) < 1e-13
 
 
+@pytest.mark.parametrize("shape", [(2, 2, 2), (2, 4, 6), (4, 4, 4), (6, 2, 4)])
+def test_antiperiodic_local_energy_difference(oracle_mod, shape):
+    """The same identity on a lattice anti-periodic along z (the bond across
+    the z boundary couples S_i to -S_j), including nz = 2, where both z
+    neighbours of a site are the same site."""
+    p = inputs.random_params(3 * sum(shape))
+    nx, ny, nz = shape
+    L = oracle_mod.OracleLattice(nx, ny, nz, **p, init=None, boundary_z="antiperiodic")
+    n = nx * ny * nz
+    S = inputs.random_unit_spins(n, 23)
+    L.set_spins(S)
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        i = int(rng.integers(0, n))
+        new = inputs.random_unit_spins(1, int(rng.integers(0, 10 ** 6)))[0]
+        e0 = L.total_energy()
+        d_local = L.local_energy(i, new) - L.local_energy(i, S[i])
+        S2 = S.copy()
+        S2[i] = new
+        L.set_spins(S2)
+        e1 = L.total_energy()
+        L.set_spins(S)
+        assert abs((e1 - e0) - d_local) < 1e-12 * max(1.0, abs(e0))
+
+
+def test_antiperiodic_closed_form_energies(oracle_mod):
+    """Uniform state: the nx*ny bonds across the z boundary each cost 2J, so
+    E = -3JN + 2J nx ny.  The uniform twist S(z) = (sin(pi z/nz), 0,
+    cos(pi z/nz)) closes on itself through the boundary: every z bond has
+    the angle pi/nz, so E = -J N (2 + cos(pi/nz))."""
+    nx, ny, nz, J = 4, 6, 10, 1.3
+    n = nx * ny * nz
+    L = oracle_mod.OracleLattice(nx, ny, nz, J=J, boundary_z="antiperiodic")
+    assert abs(L.total_energy() - (-3 * J * n + 2 * J * nx * ny)) < 1e-11
+    z = np.repeat(np.arange(nz), nx * ny)
+    S = np.stack([np.sin(np.pi * z / nz), np.zeros(n), np.cos(np.pi * z / nz)], axis=1)
+    L.set_spins(S)
+    assert abs(L.total_energy() - (-J * n * (2 + np.cos(np.pi / nz)))) < 1e-11
+    P = oracle_mod.OracleLattice(nx, ny, nz, J=J)
+    P.set_spins(S)
+    # periodic: the bond from plane nz-1 back to plane 0 has the angle pi (nz-1)/nz
+    ref = -J * n * 2 - J * nx * ny * ((nz - 1) * np.cos(np.pi / nz) + np.cos(np.pi * (nz - 1) / nz))
+    assert abs(P.total_energy() - ref) < 1e-11
+
+
 # --------------------------------------------------------------------------
 # Chain mechanics
 # --------------------------------------------------------------------------

@@ -115,3 +115,61 @@ def test_constrained_reference_torque_integrates_to_free_energy():
     ref = Kc * A.cubic_f(np.array(th, dtype=float), 0.0)
     assert np.max(np.abs(F - ref)) < 0.03 * Kc / 4, (F, ref)
     assert abs(F[9] - Kc / 4) < 0.03 * Kc / 4          # theta = 45: the <110> direction
+
+
+def test_wall_fit_recovers_synthetic_profiles():
+    """tanh profiles placed anywhere in an anti-periodic box (also across its
+    boundary), with noise, are fitted back."""
+    from paper_2103_03517_amd import walls as W
+    rng = np.random.default_rng(2)
+    nz = 256
+    for z0, d, m in [(128.0, 20.0, 0.9), (3.5, 12.0, 0.7), (250.2, 30.0, 0.5), (60.0, 8.0, 0.95)]:
+        z = np.arange(nz)
+        # the twisted profile: F(z0 + u + k nz) = (-1)^k F(z0 + u), u in [-nz/2, nz/2)
+        k = np.floor((z - z0 + nz / 2) / nz)
+        u = z - z0 - k * nz
+        f = (-1.0) ** k * m * np.tanh(-np.pi * u / d) + rng.normal(0, 0.01, nz)
+        mm, zz, dd = W.fit_wall(f)
+        assert abs(mm - m) < 0.01, (z0, mm)
+        assert abs(dd / d - 1) < 0.03, (z0, dd)
+        dz = (zz - z0 + nz / 2) % nz - nz / 2
+        assert abs(dz) < 0.5, (z0, zz)
+
+
+def test_reference_wall_width_at_low_temperature():
+    """The CPU reference relaxes a sharp wall in an anti-periodic 2x2x64
+    column at T -> 0 to the width pi sqrt(J/(2 Ku)) of the continuum Bloch
+    wall (discreteness corrections are O(1/Delta^2) for Delta of ~10 sites)."""
+    from oracle import oracle as O
+    from paper_2103_03517_amd import walls as W
+    J, Ku = 1.0, 0.05
+    o = O.OracleLattice(2, 2, 64, J=J, Ku=Ku, seed=2, boundary_z="antiperiodic", init=None)
+    o.set_spins(W.initial_wall(2, 2, 64))
+    o.sweep(0.002, 3000)
+    prof = o.spins().reshape(64, 4, 3).mean(axis=1)[:, 2]
+    m, z0, d = W.fit_wall(prof)
+    d0 = W.zero_temperature_width(J, Ku)
+    assert abs(m - 1) < 0.01
+    assert abs(d / d0 - 1) < 0.03, (d, d0)
+    assert abs(W.exchange_stiffness(Ku, d) - J / 2) < 0.03 * J
+
+
+def test_reference_uniaxial_torque_gives_Ku_sin2():
+    """Uniaxial term along z on the CPU reference at T -> 0: the integrated
+    torque is Ku sin^2 theta and the amplitude fit returns Ku."""
+    from oracle import oracle as O
+    from paper_2103_03517_amd import anisotropy as A
+    Ku, T = 0.03, 0.002
+    th = [0, 15, 30, 45, 60, 75, 90]
+    scan = []
+    for t in th:
+        e = A.e_c(t, 0.0)
+        o = O.OracleLattice(4, 4, 4, J=1.0, Ku=Ku, eu=(0, 0, 1), seed=5, init="aligned", init_dir=tuple(e))
+        o.constrained_sweep(T, tuple(e), 40)
+        o.constrained_sweep(T, tuple(e), 60, sample=True)
+        ob = o.observables(T)
+        scan.append({"theta": t, "phi": 0.0, "T": T, "E_anis": ob["mean_Eanis"], "torque": ob["mean_torque"]})
+    res = A.analyse(scan, {}, Ku, kind="uniaxial")
+    row = res["rows"][0]
+    assert abs(row["K_torque"] / Ku - 1) < 0.03, row
+    assert abs(row["K_energy"] / Ku - 1) < 0.03, row
