@@ -61,8 +61,9 @@ typedef struct hmc_lattice hmc_lattice;
 /* Lattice and model parameters (Eq. 2, Sec. 3 of the paper). */
 typedef struct {
     int32_t  nx, ny, nz;    /* each even and >= 2 (the red/black colouring of a
-                               periodic axis needs an even length, Sec. 2);
-                               nx <= 1024; nx*ny*nz < 2^32 and
+                               periodic axis needs an even length, Sec. 2),
+                               except nz >= 1 of any parity with an open z
+                               boundary; nx <= 1024; nx*ny*nz < 2^32 and
                                nx*ny*nz*precision/16 < 2^32 bytes */
     int32_t  precision;     /* 32: FP32 spins and energy changes, FP64 sums;
                                64: FP64 throughout */
@@ -79,7 +80,12 @@ typedef struct {
     int32_t  boundary_z;    /* 0: periodic along z; 1: anti-periodic along z (the
                                bond between planes nz-1 and 0 couples S_i to -S_j),
                                which holds one domain wall across z (the domain-wall
-                               method of Sec. 3); x and y stay periodic */
+                               method of Sec. 3); 2: open along z (no bond between
+                               planes nz-1 and 0: a film, Sec. 4); x and y stay
+                               periodic */
+    int32_t  bond_masks;    /* 1: keep a per-site mask of active bonds (set with
+                               hmc_set_bond_masks; every bond active until then),
+                               1 byte per spin more in the workspace; 0: none */
 } hmc_params;
 
 /* Observables.  The instantaneous values describe the spins at the time of
@@ -165,6 +171,17 @@ int hmc_observables(hmc_lattice* L, hmc_obs* out);
 /* Clears the accumulators (not the spins, cone angle or sweep counter). */
 int hmc_reset_stats(hmc_lattice* L);
 
+/* Bond masks of a lattice created with bond_masks = 1: host_mask holds one
+ * byte per site in site order (i = x + nx*(y + ny*z)); bit k set means the
+ * bond to neighbour k is active, in the order x-, x+, y-, y+, z-, z+ (bits
+ * 6-7 must be clear).  A cut bond carries no exchange: the intergrain bonds
+ * of a granular film (Sec. 4).  Each bond must be cut or kept at both ends
+ * (checked; bonds across an open z boundary are not checked, they do not
+ * exist).  The masks are configuration, not chain state: state images do
+ * not carry them.  Synchronises.  Errors: HMC_EINVAL (no masks, asymmetric
+ * or out-of-range bits), HMC_ENOMEM, HMC_EHIP. */
+int hmc_set_bond_masks(hmc_lattice* L, const uint8_t* host_mask);
+
 /* Mean spin of every z plane (a slice of nx*ny sites, both colours) of the
  * current spins: host_out receives 3*nz doubles, plane z at 3z .. 3z+2.  The
  * magnetisation profile across a wall held by the anti-periodic boundary
@@ -235,8 +252,9 @@ size_t hmc_batch_workspace_bytes(int32_t count);
 /* Builds a batch over lattices[0 .. count-1] (distinct handles, one
  * precision, one stream).  The launch shape of each lattice is the one set
  * by hmc_set_launch (a later change is picked up by the next batch call).
- * Errors: HMC_EINVAL (null, duplicate, mixed precision or stream),
- * HMC_ENOMEM (workspace too small or misaligned), HMC_EHIP. */
+ * Lattices with bond masks are not accepted (they are swept alone).
+ * Errors: HMC_EINVAL (null, duplicate, mixed precision or stream, bond
+ * masks), HMC_ENOMEM (workspace too small or misaligned), HMC_EHIP. */
 int hmc_batch_create(hmc_lattice* const* lattices, int32_t count, void* dev_ws, size_t ws_bytes,
                      hmc_batch** out);
 

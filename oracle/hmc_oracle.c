@@ -66,7 +66,8 @@ struct oracle_lattice {
     double J, Ku, eu[3], Kc, h[3];
     uint64_t seed;
     uint32_t instance;
-    int32_t apz;        /* 1: anti-periodic along z */
+    int32_t apz;        /* z boundary: 0 periodic, 1 anti-periodic, 2 open */
+    uint8_t* mask;      /* per-site active-bond bits (x-, x+, y-, y+, z-, z+), or NULL */
     int32_t theta;
     int64_t sweep;
     int64_t accepted_last;
@@ -185,9 +186,11 @@ int64_t oracle_site_of(const oracle_lattice* L, int32_t colour, int64_t idx)
     return s;
 }
 
-/* Neighbours of site i in the order x-, x+, y-, y+, z-, z+ (periodic), and
- * the sign each one enters the exchange with: -1 for a bond that crosses the
- * z boundary of an anti-periodic lattice, else +1. */
+/* Neighbours of site i in the order x-, x+, y-, y+, z-, z+ (periodic
+ * indexing), and the weight each one enters the exchange with: -1 for a bond
+ * that crosses the z boundary of an anti-periodic lattice, 0 for one that
+ * crosses an open z boundary or whose bit is clear in the site's bond mask,
+ * else +1. */
 static void neighbours(const oracle_lattice* L, int64_t i, int64_t nb[6], double sg[6])
 {
     int64_t x, y, z;
@@ -200,9 +203,13 @@ static void neighbours(const oracle_lattice* L, int64_t i, int64_t nb[6], double
     nb[5] = site_id(L, x, y, (z + 1) % L->nz);
     for (int k = 0; k < 6; ++k) sg[k] = 1.0;
     if (L->apz) {
-        if (z == 0) sg[4] = -1.0;
-        if (z == L->nz - 1) sg[5] = -1.0;
+        const double w = L->apz == 1 ? -1.0 : 0.0;
+        if (z == 0) sg[4] = w;
+        if (z == L->nz - 1) sg[5] = w;
     }
+    if (L->mask)
+        for (int k = 0; k < 6; ++k)
+            if (!((L->mask[i] >> k) & 1u)) sg[k] = 0.0;
 }
 
 static double dot3(const double a[3], const double b[3])
@@ -243,7 +250,7 @@ static void energy_parts(const oracle_lattice* L, double* e_exch, double* e_uni,
         double sg[6];
         neighbours(L, i, nb, sg);
         const double* s = &L->S[3 * i];
-        ex += -L->J * (dot3(s, &L->S[3 * nb[1]]) + dot3(s, &L->S[3 * nb[3]]) +
+        ex += -L->J * (sg[1] * dot3(s, &L->S[3 * nb[1]]) + sg[3] * dot3(s, &L->S[3 * nb[3]]) +
                        sg[5] * dot3(s, &L->S[3 * nb[5]]));
         double se = dot3(s, L->eu);
         eu += -L->Ku * se * se;
@@ -350,7 +357,9 @@ oracle_lattice* oracle_create(int32_t nx, int32_t ny, int32_t nz,
                               uint64_t seed, uint32_t instance,
                               int32_t theta0_deg)
 {
-    if (nx < 2 || ny < 2 || nz < 2 || (nx & 1) || (ny & 1) || (nz & 1))
+    /* an odd nz is only meaningful with the open z boundary (set after
+     * creation); the sweeps refuse it otherwise */
+    if (nx < 2 || ny < 2 || nz < 1 || (nx & 1) || (ny & 1))
         return NULL;
     oracle_lattice* L = (oracle_lattice*)calloc(1, sizeof(oracle_lattice));
     if (!L) return NULL;
@@ -370,9 +379,28 @@ oracle_lattice* oracle_create(int32_t nx, int32_t ny, int32_t nz,
     return L;
 }
 
-void oracle_set_boundary_z(oracle_lattice* L, int32_t antiperiodic)
+void oracle_set_boundary_z(oracle_lattice* L, int32_t mode)
 {
-    L->apz = antiperiodic ? 1 : 0;
+    L->apz = (mode == 1 || mode == 2) ? mode : 0;
+}
+
+int oracle_set_bond_masks(oracle_lattice* L, const uint8_t* mask)
+{
+    if (!mask) {
+        free(L->mask);
+        L->mask = NULL;
+        return 0;
+    }
+    if (!L->mask) L->mask = (uint8_t*)malloc((size_t)L->n);
+    if (!L->mask) return -1;
+    memcpy(L->mask, mask, (size_t)L->n);
+    return 0;
+}
+
+/* A checkerboard pass needs a bipartite lattice: an odd periodic nz is not. */
+static int sweepable(const oracle_lattice* L)
+{
+    return !((L->nz & 1) && L->apz != 2);
 }
 
 void oracle_destroy(oracle_lattice* L)
@@ -380,6 +408,7 @@ void oracle_destroy(oracle_lattice* L)
     if (!L) return;
     free(L->S);
     free(L->hist);
+    free(L->mask);
     free(L);
 }
 
@@ -554,6 +583,7 @@ static int metropolis_site(oracle_lattice* L, int64_t i, const double u[4],
 
 int64_t oracle_sweep(oracle_lattice* L, double T, int32_t n_sweeps, int32_t sample)
 {
+    if (!sweepable(L)) return -1;
     for (int32_t it = 0; it < n_sweeps; ++it) {
         int64_t accepted = 0;
         double c1 = cone_c1(L->theta);
@@ -582,6 +612,7 @@ int64_t oracle_constrained_sweep(oracle_lattice* L, double T, const double eC_in
                                  int32_t n_sweeps, int32_t sample,
                                  int32_t exact_serial)
 {
+    if (!sweepable(L)) return -1;
     double len = sqrt(dot3(eC_in, eC_in));
     double eC[3] = { eC_in[0] / len, eC_in[1] / len, eC_in[2] / len };
     int64_t Nc = L->n / 2;
@@ -654,6 +685,7 @@ int64_t oracle_constrained_sweep(oracle_lattice* L, double T, const double eC_in
 int64_t oracle_serial_random_sweep(oracle_lattice* L, double T, int32_t n_sweeps,
                                    int32_t sample)
 {
+    if (!sweepable(L)) return -1;
     int64_t* order = (int64_t*)malloc((size_t)L->n * sizeof(int64_t));
     if (!order) return -1;
     for (int32_t it = 0; it < n_sweeps; ++it) {
@@ -690,6 +722,7 @@ int64_t oracle_serial_random_sweep(oracle_lattice* L, double T, int32_t n_sweeps
  * inverting its distribution function. */
 void oracle_heatbath_sweep(oracle_lattice* L, double T, int32_t n_sweeps, int32_t sample)
 {
+    if (!sweepable(L)) return;
     for (int32_t it = 0; it < n_sweeps; ++it) {
         for (int64_t i = 0; i < L->n; ++i) {
             int64_t nb[6];

@@ -62,8 +62,15 @@ void    oracle_destroy(oracle_lattice* L);
 /* Initial states. */
 /* Boundary along z: 0 periodic (the default), 1 anti-periodic (the bond
  * between planes nz-1 and 0 enters the exchange with a minus sign; the
- * domain-wall method of Sec. 3). */
-void    oracle_set_boundary_z(oracle_lattice* L, int32_t antiperiodic);
+ * domain-wall method of Sec. 3), 2 open (no bond across the z boundary: a
+ * film, Sec. 4).  An odd nz is accepted by oracle_create for the open
+ * boundary only: the sweeps return -1 for an odd nz that is not open. */
+void    oracle_set_boundary_z(oracle_lattice* L, int32_t mode);
+/* Per-site bond masks (N bytes in site order; bit k set = bond k active, in
+ * the neighbour order x-, x+, y-, y+, z-, z+), copied; NULL restores every
+ * bond.  A bond must be set or clear in both of its sites.  Used for
+ * granular films, whose bonds between grains carry no exchange (Sec. 4). */
+int     oracle_set_bond_masks(oracle_lattice* L, const uint8_t* mask);
 void    oracle_init_aligned(oracle_lattice* L, const double dir[3]);
 void    oracle_init_random(oracle_lattice* L);
 void    oracle_set_spins(oracle_lattice* L, const double* S);

@@ -57,6 +57,8 @@ def _load():
     lib.oracle_destroy.argtypes = [vp]
     lib.oracle_init_aligned.argtypes = [vp, D3]
     lib.oracle_set_boundary_z.argtypes = [vp, ctypes.c_int32]
+    lib.oracle_set_bond_masks.argtypes = [vp, ctypes.c_void_p]
+    lib.oracle_set_bond_masks.restype = ctypes.c_int
     lib.oracle_init_random.argtypes = [vp]
     lib.oracle_set_spins.argtypes = [vp, D3]
     lib.oracle_get_spins.argtypes = [vp, D3]
@@ -164,7 +166,8 @@ class OracleLattice:
                                   int(seed), int(instance), int(theta0_deg))
         if not self.h_:
             raise ValueError("invalid oracle lattice parameters")
-        apz = {"periodic": 0, "antiperiodic": 1}[boundary_z] if isinstance(boundary_z, str) else int(boundary_z)
+        apz = ({"periodic": 0, "antiperiodic": 1, "open": 2}[boundary_z] if isinstance(boundary_z, str)
+               else int(boundary_z))
         L.oracle_set_boundary_z(self.h_, apz)
         if init == "aligned":
             _, pd = _d3(init_dir)
@@ -178,6 +181,15 @@ class OracleLattice:
         if getattr(self, "h_", None):
             _load().oracle_destroy(self.h_)
             self.h_ = None
+
+    def set_bond_masks(self, mask):
+        """mask: N uint8 in site order (bit k = bond x-, x+, y-, y+, z-, z+ active), or None."""
+        if mask is None:
+            _load().oracle_set_bond_masks(self.h_, None)
+            return
+        self._mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(self.n))
+        if _load().oracle_set_bond_masks(self.h_, self._mask.ctypes.data) != 0:
+            raise MemoryError("bond masks")
 
     def spins(self):
         out = np.zeros((self.n, 3))

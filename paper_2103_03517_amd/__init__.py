@@ -29,7 +29,7 @@ class Params(ctypes.Structure):
         ("Kc", ctypes.c_double), ("h", ctypes.c_double * 3),
         ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32),
         ("init", ctypes.c_int32), ("init_dir", ctypes.c_double * 3),
-        ("theta0_deg", ctypes.c_int32), ("boundary_z", ctypes.c_int32),
+        ("theta0_deg", ctypes.c_int32), ("boundary_z", ctypes.c_int32), ("bond_masks", ctypes.c_int32),
     ]
 
 
@@ -56,7 +56,8 @@ TIMING_KINDS = ("pass", "constrained", "reduce", "other")
 
 # every function declared in include/hmc.h
 SYMBOLS = ("hmc_workspace_bytes", "hmc_init_lattice", "hmc_sweep", "hmc_constrained_sweep",
-           "hmc_observables", "hmc_reset_stats", "hmc_plane_means", "hmc_copy_spins", "hmc_state_bytes",
+           "hmc_observables", "hmc_reset_stats", "hmc_set_bond_masks", "hmc_plane_means", "hmc_copy_spins",
+           "hmc_state_bytes",
            "hmc_get_state", "hmc_set_state", "hmc_set_launch", "hmc_get_launch",
            "hmc_set_timing", "hmc_read_timing", "hmc_destroy", "hmc_strerror",
            "hmc_last_error", "hmc_batch_workspace_bytes", "hmc_batch_create", "hmc_batch_sweep",
@@ -89,6 +90,8 @@ def lib():
     L.hmc_observables.argtypes = [vp, P(Obs)]
     L.hmc_reset_stats.restype = i32
     L.hmc_reset_stats.argtypes = [vp]
+    L.hmc_set_bond_masks.restype = i32
+    L.hmc_set_bond_masks.argtypes = [vp, ctypes.c_void_p]
     L.hmc_plane_means.restype = i32
     L.hmc_plane_means.argtypes = [vp, P(dbl)]
     L.hmc_copy_spins.restype = i32
@@ -149,7 +152,7 @@ class HmcError(RuntimeError):
 
 def make_params(nx, ny, nz, precision=64, J=1.0, Ku=0.0, eu=(0.0, 0.0, 1.0), Kc=0.0,
                 h=(0.0, 0.0, 0.0), seed=1, instance=0, init="aligned", init_dir=(0.0, 0.0, 1.0),
-                theta0_deg=30, boundary_z="periodic"):
+                theta0_deg=30, boundary_z="periodic", bond_masks=False):
     p = Params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.precision = int(precision)
@@ -161,8 +164,9 @@ def make_params(nx, ny, nz, precision=64, J=1.0, Ku=0.0, eu=(0.0, 0.0, 1.0), Kc=
     p.init = {"aligned": 0, "random": 1}[init] if isinstance(init, str) else int(init)
     p.init_dir[:] = [float(v) for v in init_dir]
     p.theta0_deg = int(theta0_deg)
-    p.boundary_z = ({"periodic": 0, "antiperiodic": 1}[boundary_z] if isinstance(boundary_z, str)
+    p.boundary_z = ({"periodic": 0, "antiperiodic": 1, "open": 2}[boundary_z] if isinstance(boundary_z, str)
                     else int(boundary_z))
+    p.bond_masks = int(bool(bond_masks))
     return p
 
 
@@ -237,6 +241,11 @@ class Lattice:
 
     def reset_stats(self):
         self._check(self._lib.hmc_reset_stats(self._h))
+
+    def set_bond_masks(self, mask):
+        """mask: one uint8 per site in site order (bits x-, x+, y-, y+, z-, z+ = bond active)."""
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(self.n))
+        self._check(self._lib.hmc_set_bond_masks(self._h, m.ctypes.data))
 
     def plane_means(self):
         """Mean spin of every z plane of the current spins, shape (nz, 3)."""

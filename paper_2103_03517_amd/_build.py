@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhmc.so")
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, "hmc_api.cpp"), os.path.join(CSRC, "hmc_batch.cpp"),
-           os.path.join(CSRC, "hmc_kernels.hip")]
+           os.path.join(CSRC, "hmc_kernels.hip"), os.path.join(CSRC, "hmc_batch_kernels.hip"),
+           os.path.join(CSRC, "hmc_masked_kernels.hip")]
 ARCH = os.environ.get("HMC_OFFLOAD_ARCH", "gfx950")
 
 
@@ -29,10 +30,26 @@ def flags():
 
 
 def build(verbose: bool = False) -> str:
-    cmd = [hipcc()] + flags() + ["-shared", "-o", LIB + ".tmp"] + SOURCES
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    """Compiles every source to an object in parallel, then links."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    with tempfile.TemporaryDirectory(prefix="hmc_build_") as tmp:
+        objs = [os.path.join(tmp, os.path.basename(src) + ".o") for src in SOURCES]
+        cmds = [[hipcc()] + flags() + ["-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            results = list(ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds))
+        for c, r in zip(cmds, results):
+            if r.stdout or r.stderr:
+                print(r.stdout + r.stderr, end="", flush=True)
+            if r.returncode != 0:
+                raise subprocess.CalledProcessError(r.returncode, c)
+        link = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

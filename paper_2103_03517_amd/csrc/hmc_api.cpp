@@ -100,11 +100,17 @@ int validate(const hmc_params* p, char* msg, size_t n)
 {
     if (!p) { snprintf(msg, n, "null parameter block"); return HMC_EINVAL; }
     const int32_t d[3] = {p->nx, p->ny, p->nz};
-    for (int i = 0; i < 3; ++i)
-        if (d[i] < 2 || (d[i] & 1)) {
-            snprintf(msg, n, "lattice dimensions must be even and >= 2 (got %d x %d x %d)", p->nx, p->ny, p->nz);
+    // x and y are periodic and must be even for the red/black colouring; z
+    // too unless it is open, where any nz >= 1 is allowed
+    const bool open_z = p->boundary_z == 2;
+    for (int i = 0; i < 3; ++i) {
+        const bool free_axis = i == 2 && open_z;
+        if (free_axis ? d[i] < 1 : (d[i] < 2 || (d[i] & 1))) {
+            snprintf(msg, n, "lattice dimensions must be even and >= 2 (nz >= 1 with an open z boundary; "
+                             "got %d x %d x %d)", p->nx, p->ny, p->nz);
             return HMC_EDIM;
         }
+    }
     if (p->nx > 1024) { snprintf(msg, n, "nx must be <= 1024 (got %d)", p->nx); return HMC_EDIM; }
     const uint64_t N = (uint64_t)p->nx * (uint64_t)p->ny * (uint64_t)p->nz;
     if (N >= (1ull << 32)) { snprintf(msg, n, "nx*ny*nz must be < 2^32"); return HMC_EDIM; }
@@ -131,8 +137,12 @@ int validate(const hmc_params* p, char* msg, size_t n)
         snprintf(msg, n, "theta0_deg must be in [1, 180] (got %d)", p->theta0_deg);
         return HMC_EINVAL;
     }
-    if (p->boundary_z != 0 && p->boundary_z != 1) {
-        snprintf(msg, n, "boundary_z must be 0 (periodic) or 1 (anti-periodic)");
+    if (p->boundary_z < 0 || p->boundary_z > 2) {
+        snprintf(msg, n, "boundary_z must be 0 (periodic), 1 (anti-periodic) or 2 (open)");
+        return HMC_EINVAL;
+    }
+    if (p->bond_masks != 0 && p->bond_masks != 1) {
+        snprintf(msg, n, "bond_masks must be 0 or 1");
         return HMC_EINVAL;
     }
     return HMC_OK;
@@ -160,6 +170,8 @@ Layout layout_for(const hmc_params* p)
     off += align_up((size_t)L.max_blocks * hmc::kNumPart * sizeof(double), hmc::kAlign);
     L.off_cnt = off;
     off += align_up((size_t)L.max_blocks * 2 * sizeof(uint32_t), hmc::kAlign);
+    L.off_mask = off;
+    if (p->bond_masks) off += align_up(2 * Nc, hmc::kAlign);
     L.total = off;
     return L;
 }
@@ -168,7 +180,7 @@ struct StateHeader {
     uint32_t magic, precision;
     int32_t nx, ny, nz, boundary_z;
     uint64_t seed;
-    uint32_t instance, pad2;
+    uint32_t instance, bond_masks;
     double J, Ku, eu[3], Kc, h[3];
 };
 
@@ -280,7 +292,8 @@ int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes, void* h
     d.key1 = (uint32_t)(p->seed >> 32);
     d.instance = p->instance;
     d.init_mode = p->init;
-    d.apz = p->boundary_z;
+    d.zbound = p->boundary_z;
+    d.mask = p->bond_masks ? reinterpret_cast<uint8_t*>(base + lay.off_mask) : nullptr;
 
     // 1 - cos(theta) = 2 sin^2(theta/2) for theta = 0..180 degrees
     for (int th = 0; th <= 180; ++th) {
@@ -300,6 +313,8 @@ int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes, void* h
                            L->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d.st, &L->init_state, sizeof(DevState), hipMemcpyHostToDevice, L->stream);
+    // every bond active until hmc_set_bond_masks says otherwise
+    if (e == hipSuccess && d.mask) e = hipMemsetAsync(d.mask, 0x3F, 2 * (size_t)d.Nc, L->stream);
     if (e != hipSuccess) { delete L; return HMC_EHIP; }
     st = launch(L, 3, "init kernel", [&] { return hmc::launch_init(L->d, L->stream); });
     if (st == HMC_OK) st = measure(L);
@@ -459,6 +474,52 @@ int hmc_reset_stats(hmc_lattice* L)
     return HMC_OK;
 }
 
+int hmc_set_bond_masks(hmc_lattice* L, const uint8_t* host_mask)
+{
+    if (!L || !host_mask) return HMC_EINVAL;
+    const DevLattice& d = L->d;
+    if (!d.mask) return fail(L, HMC_EINVAL, "the lattice was created without bond masks");
+    const int64_t nx = d.nx, ny = d.ny, nz = d.nz;
+    // a bond must be active or cut at both of its ends (bit k of a site and
+    // the opposite bit of its neighbour k); bonds across an open z boundary
+    // do not exist and are not checked
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                const int64_t i = x + nx * (y + ny * z);
+                const uint8_t m = host_mask[i];
+                if (m & 0xC0u) return fail(L, HMC_EINVAL, "bond masks use bits 0..5 only");
+                const int64_t jx = ((x + 1) % nx) + nx * (y + ny * z);
+                const int64_t jy = x + nx * (((y + 1) % ny) + ny * z);
+                const int64_t jz = x + nx * (y + ny * ((z + 1) % nz));
+                const bool zcut = d.zbound == 2 && z == nz - 1;
+                if (((m >> 1) & 1u) != (host_mask[jx] & 1u) || ((m >> 3) & 1u) != ((host_mask[jy] >> 2) & 1u) ||
+                    (!zcut && ((m >> 5) & 1u) != ((host_mask[jz] >> 4) & 1u))) {
+                    char msg[160];
+                    snprintf(msg, sizeof(msg), "bond masks are not symmetric at site (%lld, %lld, %lld)",
+                             (long long)x, (long long)y, (long long)z);
+                    return fail(L, HMC_EINVAL, msg);
+                }
+            }
+    std::vector<uint8_t> split;
+    try {
+        split.resize(2 * (size_t)d.Nc);
+    } catch (...) {
+        return fail(L, HMC_ENOMEM, "host staging buffer");
+    }
+    // colour-split order: site i = 2k + p has colour c = (x + y + z) & 1
+    for (int64_t k = 0; k < d.Nc; ++k) {
+        const int64_t r = k / d.hx;
+        const int64_t y = r % d.ny, z = r / d.ny;
+        for (int c = 0; c < 2; ++c) split[(size_t)c * d.Nc + k] = host_mask[2 * k + ((y + z + c) & 1)];
+    }
+    hipError_t e = hipMemcpyAsync(d.mask, split.data(), split.size(), hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "copying the bond masks", e);
+    L->m_valid = false;
+    return HMC_OK;
+}
+
 int hmc_plane_means(hmc_lattice* L, double* host_out)
 {
     if (!L || !host_out) return HMC_EINVAL;
@@ -545,6 +606,7 @@ static void fill_header(const hmc_lattice* L, StateHeader* h)
     h->nz = L->p.nz;
     h->boundary_z = L->p.boundary_z;
     h->seed = L->p.seed;
+    h->bond_masks = (uint32_t)L->p.bond_masks;
     h->instance = L->p.instance;
     h->J = L->p.J;
     h->Ku = L->p.Ku;

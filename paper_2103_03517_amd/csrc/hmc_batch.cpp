@@ -277,8 +277,9 @@ int hmc_batch_create(hmc_lattice* const* lattices, int32_t count, void* dev_ws, 
     if (!out) return HMC_EINVAL;
     *out = nullptr;
     if (!lattices || count < 1 || count > kMaxBatch) return HMC_EINVAL;
+    // lattices with bond masks run the masked pass, which batches do not have
     for (int32_t i = 0; i < count; ++i)
-        if (!lattices[i]) return HMC_EINVAL;
+        if (!lattices[i] || lattices[i]->d.mask) return HMC_EINVAL;
     std::vector<hmc_lattice*> sorted(lattices, lattices + count);
     std::sort(sorted.begin(), sorted.end());
     if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return HMC_EINVAL;

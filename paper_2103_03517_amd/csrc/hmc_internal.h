@@ -71,7 +71,8 @@ struct DevLattice {
     uint32_t key0, key1, instance;
     int32_t init_mode;
     double init_dir[3];
-    int32_t apz;              // 1: anti-periodic along z
+    int32_t zbound;           // z boundary: 0 periodic, 1 anti-periodic, 2 open
+    uint8_t* mask;            // [colour][Nc] active-bond bits, or null (every bond)
 };
 
 // Launchers (hmc_kernels.hip).  Each returns the HIP status of the launch;

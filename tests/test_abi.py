@@ -44,8 +44,9 @@ def test_strerror(hmc):
     (dict(nx=3), -2), (dict(ny=0), -2), (dict(nz=5), -2), (dict(nx=2048), -2),
     (dict(precision=16), -1), (dict(J=float("nan")), -1), (dict(eu=(0, 0, 0)), -1),
     (dict(h=(0, float("inf"), 0)), -1), (dict(theta0_deg=0), -1), (dict(theta0_deg=181), -1),
-    (dict(init=2), -1), (dict(init_dir=(0, 0, 0)), -1), (dict(boundary_z=2), -1),
-    (dict(boundary_z=-1), -1),
+    (dict(init=2), -1), (dict(init_dir=(0, 0, 0)), -1), (dict(boundary_z=3), -1),
+    (dict(boundary_z=-1), -1), (dict(nz=5, boundary_z=1), -2),
+    (dict(nz=0, boundary_z=2), -2),
 ])
 def test_validation(hmc, kw, status):
     base = dict(nx=4, ny=4, nz=4)
@@ -77,11 +78,25 @@ def test_workspace_size_and_too_small(hmc):
                               ctypes.byref(h)) == -3
 
 
+def test_open_z_allows_any_thickness_and_masks_add_a_byte_per_spin(hmc):
+    L = hmc.lib()
+    for nz in (1, 3, 5, 6):
+        p = hmc.make_params(8, 8, nz, precision=32, boundary_z="open")
+        assert L.hmc_workspace_bytes(ctypes.byref(p)) > 0, nz
+    a = L.hmc_workspace_bytes(ctypes.byref(hmc.make_params(64, 64, 16, precision=32)))
+    b = L.hmc_workspace_bytes(ctypes.byref(hmc.make_params(64, 64, 16, precision=32, bond_masks=True)))
+    assert 64 * 64 * 16 <= b - a < 64 * 64 * 16 + 1024
+    p = hmc.make_params(8, 8, 8)
+    p.bond_masks = 2
+    assert L.hmc_workspace_bytes(ctypes.byref(p)) == 0
+
+
 def test_null_handles(hmc):
     L = hmc.lib()
     assert L.hmc_sweep(None, 1.0, 1, 0) == -1
     assert L.hmc_observables(None, None) == -1
     assert L.hmc_plane_means(None, None) == -1
+    assert L.hmc_set_bond_masks(None, None) == -1
     assert L.hmc_state_bytes(None) == 0
     L.hmc_destroy(None)
     assert L.hmc_last_error(None) == b"no lattice"

@@ -214,6 +214,9 @@ def test_batch_argument_errors(H):
     with pytest.raises(H.HmcError) as e:
         H.Batch([g32, h32, g32])
     assert e.value.status == H.EINVAL
+    with pytest.raises(H.HmcError) as e:
+        H.Batch([g32, H.Lattice(4, 4, 4, precision=32, bond_masks=True)])
+    assert e.value.status == H.EINVAL
     B = H.Batch([g32, h32])
     for bad in ([1.0, 0.0], [1.0, float("nan")], [-1.0, 1.0], [1.0, float("inf")]):
         with pytest.raises(H.HmcError) as e:

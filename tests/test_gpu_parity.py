@@ -179,6 +179,62 @@ def test_antiperiodic_z_fp64_matches_reference(H, O, shape, spt, zc):
     assert g.observables()["theta_deg"] == o.counters()[0]
 
 
+# (shape, boundary, sites per thread, z chunk, cut probability): open films of
+# odd and even thickness (nz = 1 is a monolayer) and bond masks
+MASKED = [((8, 6, 5), "open", 1, 2, 0.3), ((4, 4, 1), "open", 2, 1, 0.0), ((10, 6, 3), "open", 1, 16, 0.25),
+          ((6, 10, 4), "periodic", 2, 3, 0.3), ((8, 8, 6), "antiperiodic", 4, 4, 0.2), ((34, 6, 4), "open", 1, 1, 0.4)]
+
+
+@pytest.mark.parametrize("shape,boundary,spt,zc,pcut", MASKED)
+def test_open_z_and_bond_masks_fp64_match_reference(H, O, shape, boundary, spt, zc, pcut):
+    _say("masked fp64", shape, boundary, spt, zc, pcut)
+    kw = dict(inputs.random_params(7 * sum(shape)), seed=55 + shape[2], instance=6, theta0_deg=40,
+              boundary_z=boundary)
+    n = shape[0] * shape[1] * shape[2]
+    S = inputs.random_unit_spins(n, 77)
+    mask = inputs.random_bond_masks(shape, pcut, sum(shape))
+    g = H.Lattice(*shape, precision=64, bond_masks=True, **kw)
+    o = O.OracleLattice(*shape, init=None, **kw)
+    g.set_bond_masks(mask)
+    o.set_bond_masks(mask)
+    g.set_spins(S)
+    o.set_spins(S)
+    g.set_launch(spt, zc)
+    T = 0.7
+
+    def step(s):
+        g.sweep(T, sample=(s % 2 == 1))
+        return o.sweep(T, sample=(s % 2 == 1))
+
+    _compare_every_sweep(g, o, 50, step, shape)
+    a, b = g.observables(), o.observables(T)
+    for k in ("E", "E_exch"):
+        assert abs(a[k] - b[k]) <= 1e-11 * max(1.0, abs(b[k])), k
+    assert np.allclose(a["mean_E"], b["mean_E"], rtol=1e-11, atol=1e-13)
+    eC = np.array([0.5, 0.5, 0.7071])
+    eC /= np.linalg.norm(eC)
+    for _ in range(8):
+        g.constrained_sweep(T, eC, sample=True)
+        o.constrained_sweep(T, eC, sample=True)
+        assert np.max(np.abs(g.spins() - o.spins())) <= TOL
+    assert g.observables()["theta_deg"] == o.counters()[0]
+
+
+def test_bond_mask_errors(H):
+    g = H.Lattice(4, 4, 4, precision=32)
+    with pytest.raises(H.HmcError):
+        g.set_bond_masks(np.full(64, 0x3F, dtype=np.uint8))      # created without masks
+    h = H.Lattice(4, 4, 4, precision=32, bond_masks=True)
+    bad = np.full(64, 0x3F, dtype=np.uint8)
+    bad[5] &= 0xFD                                               # x+ cut on one end only
+    with pytest.raises(H.HmcError):
+        h.set_bond_masks(bad)
+    bad = np.full(64, 0x7F, dtype=np.uint8)
+    with pytest.raises(H.HmcError):
+        h.set_bond_masks(bad)
+    h.set_bond_masks(np.full(64, 0x3F, dtype=np.uint8))
+
+
 def test_plane_means(H):
     """Mean spin per z plane equals the average of the spins of that plane."""
     shape = (10, 6, 8)

@@ -222,6 +222,52 @@ def test_antiperiodic_closed_form_energies(oracle_mod):
     assert abs(P.total_energy() - ref) < 1e-11
 
 
+@pytest.mark.parametrize("shape,boundary", [((4, 4, 5), "open"), ((2, 4, 1), "open"), ((4, 2, 4), "periodic"),
+                                            ((6, 4, 2), "antiperiodic")])
+def test_masked_local_energy_difference(oracle_mod, shape, boundary):
+    """The local/total identity with bond masks and an open or twisted z
+    boundary (odd and unit thickness included)."""
+    p = inputs.random_params(11 * sum(shape))
+    nx, ny, nz = shape
+    L = oracle_mod.OracleLattice(nx, ny, nz, **p, init=None, boundary_z=boundary)
+    L.set_bond_masks(inputs.random_bond_masks(shape, 0.35, 8))
+    n = nx * ny * nz
+    S = inputs.random_unit_spins(n, 29)
+    L.set_spins(S)
+    rng = np.random.default_rng(6)
+    for _ in range(40):
+        i = int(rng.integers(0, n))
+        new = inputs.random_unit_spins(1, int(rng.integers(0, 10 ** 6)))[0]
+        e0 = L.total_energy()
+        d_local = L.local_energy(i, new) - L.local_energy(i, S[i])
+        S2 = S.copy()
+        S2[i] = new
+        L.set_spins(S2)
+        e1 = L.total_energy()
+        L.set_spins(S)
+        assert abs((e1 - e0) - d_local) < 1e-12 * max(1.0, abs(e0))
+
+
+def test_open_and_masked_closed_forms(oracle_mod):
+    """Aligned state: an open film has 2N + nx ny (nz - 1) bonds, each worth
+    -J; with masks, E = -J times the number of active bonds (counted from
+    the masks); cutting every bond leaves no exchange."""
+    nx, ny, nz, J = 6, 4, 5, 1.2
+    n = nx * ny * nz
+    L = oracle_mod.OracleLattice(nx, ny, nz, J=J, boundary_z="open")
+    assert abs(L.total_energy() - (-J * (2 * n + nx * ny * (nz - 1)))) < 1e-11
+    M = oracle_mod.OracleLattice(nx, ny, 4, J=J)
+    mask = inputs.random_bond_masks((nx, ny, 4), 0.4, 3)
+    M.set_bond_masks(mask)
+    active = sum(int(b) for b in np.unpackbits(mask.reshape(-1, 1), axis=1)[:, 2:].ravel()) // 2
+    assert abs(M.total_energy() - (-J * active)) < 1e-11
+    M.set_bond_masks(np.zeros(nx * ny * 4, dtype=np.uint8))
+    assert abs(M.total_energy()) < 1e-14
+    # an odd periodic thickness is not bipartite: the sweeps refuse it
+    P = oracle_mod.OracleLattice(4, 4, 3, J=J)
+    assert P.sweep(1.0) == -1
+
+
 # --------------------------------------------------------------------------
 # Chain mechanics
 # --------------------------------------------------------------------------

@@ -173,3 +173,37 @@ def test_reference_uniaxial_torque_gives_Ku_sin2():
     row = res["rows"][0]
     assert abs(row["K_torque"] / Ku - 1) < 0.03, row
     assert abs(row["K_energy"] / Ku - 1) < 0.03, row
+
+
+def test_voronoi_film_masks():
+    """Grain maps cover the plane, the mean grain area matches the requested
+    diameter, and the masks cut exactly the bonds between grains, at both
+    ends, keeping every z bond."""
+    from paper_2103_03517_amd import films as F
+    g, ng = F.voronoi_grains(128, 96, 16, seed=1)
+    assert g.shape == (96, 128) and len(np.unique(g)) <= ng
+    assert abs(F.grain_areas(g).mean() / (np.pi * 16 ** 2 / 4) - 1) < 0.15
+    m = F.grain_bond_masks(g, 3).reshape(3, 96, 128)
+    for z in range(3):
+        for y in range(0, 96, 7):
+            for x in range(0, 128, 5):
+                a = int(m[z, y, x])
+                assert ((a >> 1) & 1) == (g[y, x] == g[y, (x + 1) % 128])
+                assert ((a >> 3) & 1) == (g[y, x] == g[(y + 1) % 96, x])
+                assert ((a >> 1) & 1) == (int(m[z, y, (x + 1) % 128]) & 1)
+                assert ((a >> 3) & 1) == ((int(m[z, (y + 1) % 96, x]) >> 2) & 1)
+                assert (a >> 4) & 3 == 3
+
+
+def test_multi_bloch_fit_recovers_a_two_term_mixture():
+    from paper_2103_03517_amd import films as F
+    T = np.linspace(0.05, 1.5, 30)
+    w, tc, b = np.array([0.3, 0.7]), np.array([0.9, 1.4]), np.array([0.34, 0.36])
+    m = F.multi_bloch(T, w, tc, b)
+    fw, ftc, fb, mean_tc, rms = F.fit_multi_bloch(T, m, 2, seed=1)
+    assert rms < 2e-3
+    assert abs(mean_tc - np.dot(w, tc)) < 0.03
+    # one Bloch term: Eq. 3
+    m1 = F.bloch(T, 1.44, 0.34)
+    fw, ftc, fb, mean_tc, rms = F.fit_multi_bloch(T, m1, 1)
+    assert abs(ftc[0] - 1.44) < 0.01 and abs(fb[0] - 0.34) < 0.01
