@@ -1,7 +1,8 @@
 """Compile the HIP library (csrc/) for gfx950 into paper_2103_03517_amd/libhmc.so.
 
 hipcc cross-compiles without a GPU.  Packed FP32 instructions are disabled
-for the device code.
+for the device code, and multiply-adds are contracted only within a source
+expression.
 """
 import os
 import subprocess
@@ -24,7 +25,12 @@ def hipcc():
 
 
 def flags():
-    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
+    # -ffp-contract=on: multiply-adds are fused only within one source
+    # expression, so the same device function rounds identically in every
+    # kernel it is inlined into (the single-lattice and the batch passes);
+    # the default (fast) lets the backend fuse across statements depending on
+    # the surrounding code.
+    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=on",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

@@ -148,8 +148,9 @@ def test_graph_replay_equals_eager(H):
     for rep, (n, smp) in enumerate([(7, False), (6, True), (3, True), (5, False)]):
         Be.sweep(T, n, sample=smp)
         Bg.sweep(T, n, sample=smp)
-        # eager work of the program between replays
-        for g in graph:
+        # eager work of the program between replays (a measurement refreshes
+        # the instantaneous M and E kept in the state, so both sides do it)
+        for g in graph + eager:
             g.observables()
         for i, (a, b) in enumerate(zip(eager, graph)):
             assert a.get_state() == b.get_state(), (rep, MIX[i])

@@ -21,7 +21,9 @@ def P():
 
 @pytest.mark.parametrize("T", [0.3, 0.8, 1.2])
 def test_fp32_matches_fp64_statistically(P, T):
-    kw = dict(size=64, equil=1000, samples=24000, block=600, init="aligned", Ku=0.005)
+    # 40 blocks of 2400 sweeps: blocks much longer than the autocorrelation
+    # time of m at these temperatures, so the batch-means errors are honest
+    kw = dict(size=64, equil=2000, samples=96000, block=2400, init="aligned", Ku=0.005)
     r32 = P.mt_sweep([T], precision=32, seed=11, **kw)[0]
     r64 = P.mt_sweep([T], precision=64, seed=12, **kw)[0]
     print(f"T={T}: m32={r32['m'][0]:.6f}+-{r32['se_m'][0]:.1e} m64={r64['m'][0]:.6f}+-"
