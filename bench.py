@@ -31,8 +31,11 @@ if ROOT not in sys.path:
 METRIC = "spin updates/sec at 256³ (FP32 vs FP64); batched M(T) jobs/s + p99 latency"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, public specification
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_256cubed_fp32_traffic.md")
+# everything that decides the machine code of the colour pass: its source,
+# the headers it includes and the compiler flags
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_03517_amd", "csrc", f)
-                  for f in ("hmc_kernels.hip", "hmc_device.hpp", "hmc_internal.h")]
+                  for f in ("hmc_pass.hpp", "hmc_kernels.hip", "hmc_device.hpp", "hmc_internal.h")] + \
+                 [os.path.join(ROOT, "paper_2103_03517_amd", "_build.py")]
 
 
 def log(*a):
@@ -151,7 +154,10 @@ def batch_leg(sequential=False):
                       "jobs_within_1e-3": sum(c["dm"] <= 1e-3 for c in cmp),
                       "jobs_within_3se": sum(c["dm_over_se"] <= 3.0 for c in cmp),
                       "max_dm_over_se": max(c["dm_over_se"] for c in cmp),
-                      "jobs": len(cmp)},
+                      "jobs": len(cmp),
+                      "worst": [{"edge": c["edge"], "T": round(c["T"], 4), "dm": c["dm"],
+                                 "dm_over_se": round(c["dm_over_se"], 2)}
+                                for c in sorted(cmp, key=lambda c: -c["dm_over_se"])[:5]]},
     }
     log(f"  FP32 {out['jobs_per_s']:.2f} jobs/s ({out['updates_per_s'] / 1e9:.1f} G updates/s), "
         f"FP64 {out['fp64_jobs_per_s']:.2f} jobs/s; |dm| max {out['precision']['max_abs_dm']:.2e}, "
@@ -238,6 +244,10 @@ def main():
                     help="also run the batched jobs one lattice at a time, for comparison")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run a few 256^3 FP32 sweeps and nothing else (for counter runs)")
+    ap.add_argument("--profile-constrained", action="store_true",
+                    help="run a few 128^3 FP32 constrained sweeps and nothing else")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="run a few sweeps of the 64-job batch and nothing else")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy a 1 GiB buffer a few times (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -266,6 +276,25 @@ def main():
         g.sweep(1.0, 10, sample=True)
         torch.cuda.synchronize()
         log("profile-pass: 10 sampled 256^3 FP32 sweeps (20 colour passes)")
+        return
+    if args.profile_constrained:
+        g = H.Lattice(128, 128, 128, precision=32, J=1.0, Kc=0.05, seed=7, init="aligned",
+                      init_dir=(0.6, 0.0, 0.8))
+        g.constrained_sweep(0.6, (0.6, 0.0, 0.8), 20, sample=True)
+        torch.cuda.synchronize()
+        log("profile-constrained: 20 sampled 128^3 FP32 constrained sweeps")
+        return
+    if args.profile_batch:
+        from paper_2103_03517_amd import protocols as P
+        jobs = P.c4_jobs(64)
+        lats = [H.Lattice(e, e, e, precision=32, J=1.0, Ku=0.01, seed=4, instance=i, init="aligned")
+                for i, (e, _) in enumerate(jobs)]
+        for l in lats:
+            l.set_launch(2, 16)
+        B = H.Batch(lats)
+        B.sweep([t for _, t in jobs], 20, sample=True)
+        torch.cuda.synchronize()
+        log("profile-batch: 20 sampled sweeps of the 64-job FP32 batch")
         return
     dev = torch.cuda.get_device_properties(0)
     log(f"device: {dev.name}, {dev.multi_processor_count} CUs")

@@ -10,7 +10,9 @@ e_phi = (-sin phi, cos phi, 0) costs dF = -<tau> . e_phi d(theta).  So
 
 (at T -> 0 this is K_c f(e_C) with f = ex^2 ey^2 + ex^2 ez^2 + ey^2 ez^2,
 which fixes the sign).  K(T) is the amplitude of the cubic angular
-dependence of F, fitted over the scanned directions, and the exponent n of
+dependence of F, fitted over the scanned directions (directly on the torque,
+-<tau>.e_phi = K dF/dtheta, which avoids the quadrature error of a coarse
+angle grid; F itself is also integrated), and the exponent n of
 K(T)/K(0) = m(T)^n compares with the l(l+1)/2 = 10 of Callen-Callen theory
 for the fourth-order (l = 4) cubic term.  The internal-energy route fits the
 same shape to <E_anis>(theta) instead.
@@ -41,6 +43,18 @@ def uniaxial_f(theta_deg, phi_deg):
     """Angular shape of a uniaxial term along z: 1 - cos^2 t = sin^2 t
     (E_anis = -Ku (S.z)^2 is Ku sin^2 t above its minimum)."""
     return np.sin(np.radians(theta_deg)) ** 2
+
+
+def cubic_df(theta_deg, phi_deg):
+    """d f(e_C(theta, phi)) / d theta of the cubic shape."""
+    t, p = np.radians(theta_deg), math.radians(phi_deg)
+    st, ct = np.sin(t), np.cos(t)
+    return 4 * st ** 3 * ct * math.cos(p) ** 2 * math.sin(p) ** 2 + 2 * st * ct ** 3 - 2 * st ** 3 * ct
+
+
+def uniaxial_df(theta_deg, phi_deg):
+    """d sin^2(theta) / d theta."""
+    return np.sin(2 * np.radians(theta_deg))
 
 
 def cubic_torque(theta_deg, phi_deg, Kc):
@@ -74,6 +88,19 @@ def fit_cubic_amplitude(curves, shape=None):
     return num / den
 
 
+def fit_torque_amplitude(rows, dshape):
+    """Least-squares K with -<tau>.e_phi = K dshape/dtheta over the rows
+    {theta, phi, torque}: the torque route without the quadrature error of
+    integrating over a coarse angle grid."""
+    num = den = 0.0
+    for r in rows:
+        g = -float(np.dot(np.asarray(r["torque"], dtype=float), e_phi(r["phi"])))
+        d = float(dshape(float(r["theta"]), r["phi"]))
+        num += g * d
+        den += d * d
+    return num / den
+
+
 def callen_callen_exponent(K, K0, m):
     """n of K/K0 = m^n by least squares on the logarithms, through the origin."""
     x = np.log(np.asarray(m, dtype=float))
@@ -89,6 +116,7 @@ def analyse(scan, m_of_T, Kc, kind="cubic"):
     kind: "cubic" (Kc f) or "uniaxial" (Ku sin^2 theta about z), Kc being
     the T = 0 constant of that term."""
     shape = cubic_f if kind == "cubic" else uniaxial_f
+    dshape = cubic_df if kind == "cubic" else uniaxial_df
     temps = sorted({r["T"] for r in scan})
     phis = sorted({r["phi"] for r in scan})
     out = []
@@ -103,14 +131,20 @@ def analyse(scan, m_of_T, Kc, kind="cubic"):
             E = np.array([r["E_anis"] for r in rows])
             curves_tau.append((th, F, phi))
             curves_e.append((th, E - E[0], phi))
-        out.append({"T": T, "K_torque": fit_cubic_amplitude(curves_tau, shape),
-                    "K_energy": fit_cubic_amplitude(curves_e, shape), "m": m_of_T.get(T)})
-    have_m = [r for r in out if r["m"] is not None and r["K_torque"] > 0 and 0 < r["m"] < 1]
+        out.append({"T": T, "K_torque": fit_torque_amplitude([r for r in scan if r["T"] == T], dshape),
+                    "K_torque_integrated": fit_cubic_amplitude(curves_tau, shape),
+                    "K_energy": fit_cubic_amplitude(curves_e, shape), "m": m_of_T.get(T),
+                    "F": {str(phi): [float(v) for v in c[1]] for c, phi in zip(curves_tau, phis)}})
     res = {"Kc": Kc, "rows": out}
-    if len(have_m) >= 2:
-        res["n_torque"] = callen_callen_exponent([r["K_torque"] for r in have_m], Kc, [r["m"] for r in have_m])
-        good_e = [r for r in have_m if r["K_energy"] > 0]
-        if len(good_e) >= 2:
-            res["n_energy"] = callen_callen_exponent([r["K_energy"] for r in good_e], Kc,
-                                                     [r["m"] for r in good_e])
+    # over every point with 0 < m < 1, and over the low-temperature range
+    # m > 0.6 where the Callen-Callen law is expected to hold
+    for tag, m_lo in (("", 0.0), ("_low", 0.6)):
+        have_m = [r for r in out if r["m"] is not None and r["K_torque"] > 0 and m_lo < r["m"] < 1]
+        if len(have_m) >= 2:
+            res["n_torque" + tag] = callen_callen_exponent([r["K_torque"] for r in have_m], Kc,
+                                                           [r["m"] for r in have_m])
+            good_e = [r for r in have_m if r["K_energy"] > 0]
+            if len(good_e) >= 2:
+                res["n_energy" + tag] = callen_callen_exponent([r["K_energy"] for r in good_e], Kc,
+                                                               [r["m"] for r in good_e])
     return res

@@ -29,22 +29,40 @@ import numpy as np
 from . import Batch, Lattice
 
 
+def blocking_se(x):
+    """Standard error of the mean of a correlated series of equal-length
+    block means, by the blocking method of Flyvbjerg and Petersen (J. Chem.
+    Phys. 91, 461, 1989): merge neighbouring blocks pairwise while at least
+    four remain and keep the largest batch-means error over the levels, so
+    blocks shorter than the autocorrelation time do not shrink it.  x has
+    the blocks along axis 0."""
+    x = np.asarray(x, dtype=float)
+    if len(x) < 2:
+        return np.full(x.shape[1:], np.nan)
+    best = x.std(axis=0, ddof=1) / math.sqrt(len(x))
+    while len(x) >= 8:
+        k = len(x) // 2
+        x = 0.5 * (x[0:2 * k:2] + x[1:2 * k:2])
+        best = np.maximum(best, x.std(axis=0, ddof=1) / math.sqrt(len(x)))
+    return best
+
+
 def _block_stats(blocks, n, T):
-    """Combine equal-length blocks: means, batch-means standard errors, and
-    the susceptibility of the whole window (within-block variance plus the
-    variance of the block means)."""
+    """Combine equal-length blocks: means, standard errors (blocking
+    analysis of the block means), and the susceptibility of the whole
+    window (within-block variance plus the variance of the block means)."""
     mean_m = np.array([b["mean_m"] for b in blocks])        # (nb, 4)
     var_m = np.array([b["var_m"] for b in blocks])
     mean_e = np.array([b["mean_E"] for b in blocks])
     nb = len(blocks)
     m = mean_m.mean(axis=0)
-    se_m = mean_m.std(axis=0, ddof=1) / math.sqrt(nb) if nb > 1 else np.full(4, np.nan)
+    se_m = blocking_se(mean_m)
     var_tot = var_m.mean(axis=0) + mean_m.var(axis=0)
     chi = n * var_tot / T
     chi_b = n * (var_m + (mean_m - m) ** 2) / T
-    se_chi = chi_b.std(axis=0, ddof=1) / math.sqrt(nb) if nb > 1 else np.full(4, np.nan)
+    se_chi = blocking_se(chi_b)
     e = float(mean_e.mean())
-    se_e = float(mean_e.std(ddof=1) / math.sqrt(nb)) if nb > 1 else float("nan")
+    se_e = float(blocking_se(mean_e[:, None])[0])
     return {"T": T, "m": m.tolist(), "se_m": se_m.tolist(), "E": e, "se_E": se_e,
             "chi": chi.tolist(), "se_chi": se_chi.tolist(), "blocks": nb}
 
@@ -237,8 +255,8 @@ def anisotropy_run(size=128, precision=32, thetas=tuple(range(0, 91, 10)), phis=
     return res
 
 
-def uniaxial_K(temps, size=64, precision=32, thetas=(0, 30, 60, 90), Ku=0.01, J=1.0, sweeps=3000, equil=1000,
-               seed=8):
+def uniaxial_K(temps, size=64, precision=32, thetas=(0, 15, 30, 45, 60, 75, 90), Ku=0.01, J=1.0, sweeps=3000,
+               equil=1000, seed=8):
     """K(T) of a uniaxial term along z from constrained runs at a few angles
     (torque route, anisotropy.analyse with the sin^2 shape)."""
     from . import anisotropy as A
@@ -259,19 +277,20 @@ def uniaxial_K(temps, size=64, precision=32, thetas=(0, 30, 60, 90), Ku=0.01, J=
     return {r["T"]: r["K_torque"] for r in res["rows"]}
 
 
-def wall_run(temps, shape=(64, 64, 512), precision=32, J=1.0, Ku=0.01, equil=2000, samples=4000, every=100,
+def wall_run(temps, shape=(64, 64, 512), precision=32, J=1.0, Ku=0.01, equil=5000, samples=20000, every=250,
              seed=6, K_of_T=None, log=None):
     """Domain-wall width across temperatures (Sec. 3, Eq. 5): one lattice per
-    temperature, anti-periodic along z and started from a sharp wall, all in
-    one batch; the plane profile of m_z is fitted every `every` sampled
-    sweeps and the widths averaged.  With K_of_T, A(T) = K Delta^2/pi^2."""
+    temperature, anti-periodic along z and started from the T = 0 wall
+    profile, all in one batch; the plane profile of m_z is fitted every
+    `every` sampled sweeps and the widths averaged.  With K_of_T,
+    A(T) = K Delta^2/pi^2."""
     from . import walls as Wm
     nx, ny, nz = shape
     lats = []
     for i, T in enumerate(temps):
         g = Lattice(nx, ny, nz, precision=precision, J=J, Ku=Ku, eu=(0.0, 0.0, 1.0), seed=seed, instance=i,
                     init="aligned", boundary_z="antiperiodic")
-        g.set_spins(Wm.initial_wall(nx, ny, nz))
+        g.set_spins(Wm.initial_wall(nx, ny, nz, width=Wm.zero_temperature_width(J, Ku)))
         lats.append(g)
     B = Batch(lats)
     B.sweep(list(temps), equil)

@@ -143,7 +143,7 @@ class Server:
                               seed=job.seed, instance=job.instance, init="aligned",
                               boundary_z="antiperiodic" if job.kind == "wall" else "periodic")
         if job.kind == "wall":
-            job.lattice.set_spins(W.initial_wall(*job.shape))
+            job.lattice.set_spins(W.initial_wall(*job.shape, width=W.zero_temperature_width(job.J, job.Ku)))
         if job.shape in self.shapes:
             job.lattice.set_launch(*self.shapes[job.shape])
         job.admitted = now

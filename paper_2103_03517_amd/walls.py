@@ -87,11 +87,18 @@ def zero_temperature_width(J, Ku):
     return math.pi * math.sqrt(J / (2.0 * Ku))
 
 
-def initial_wall(nx, ny, nz):
-    """Spins +z below nz/2 and -z above: one sharp wall at nz/2, and none at
-    the anti-periodic boundary.  Site order x fastest, then y, then z."""
+def initial_wall(nx, ny, nz, width=None):
+    """One wall centred between planes nz/2 - 1 and nz/2 and none at the
+    anti-periodic boundary: spins +z below, -z above.  width=None gives a
+    sharp wall; otherwise the T = 0 profile of that width, S = (sech u, 0,
+    -tanh u) with u = pi (z - z0)/width.  Site order x fastest, then y, z."""
     n = nx * ny * nz
-    z = np.repeat(np.arange(nz), nx * ny)
+    z = np.repeat(np.arange(nz), nx * ny).astype(float)
     S = np.zeros((n, 3))
-    S[:, 2] = np.where(z < nz // 2, 1.0, -1.0)
+    if width is None:
+        S[:, 2] = np.where(z < nz // 2, 1.0, -1.0)
+    else:
+        u = math.pi * (z - (nz / 2.0 - 0.5)) / width
+        S[:, 0] = 1.0 / np.cosh(u)
+        S[:, 2] = -np.tanh(u)
     return S
