@@ -190,10 +190,11 @@ template <typename R, int C, bool OBS>
 __global__ __launch_bounds__(kThreads) void nbsum_kernel(const KArgs<R> a, const Vec4<R>* aos, Vec4<R>* nbs)
 {
     __shared__ double scratch[5 * kNumPart];
-    const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
     const Vec4<R>* other = aos + (size_t)(1 - C) * a.Nc;
     Acc acc;
-    if (k < a.Nc) {
+    // grid-stride: at most kGatherBlocks work-groups, so that the finalize
+    // has few partial records to fold
+    for (uint32_t k = blockIdx.x * kThreads + threadIdx.x; k < a.Nc; k += gridDim.x * kThreads) {
         uint32_t id[6];
         bool wm, wp;
         neighbour_indices<C>(k, a.hx, a.ny, a.nz, a.P, id, wm, wp);
@@ -240,7 +241,6 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R
 {
     __shared__ double scratch[5 * kNumPart];
     Vec4<R>* own = aos + (size_t)C * a.Nc;
-    const uint32_t ia = blockIdx.x * kThreads + threadIdx.x;
     const uint32_t sweep = (uint32_t)a.st->sweep;
     const R c1 = a.c1tab[a.st->theta];
     const Model<R> m = a.m;
@@ -251,44 +251,46 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R
 
     uint32_t nacc = 0;
     Acc acc;
-    const uint32_t pos = ia < a.Nc ? unshuffle_index(ia, a.Nc, half, mask, key) : 1u;
-    if ((pos & 1u) == 0u) {
-        const uint32_t k = pos >> 1;
-        const uint32_t ja = shuffle_index(pos + 1u, a.Nc, half, mask, key);
-        const V3<R> si = ld4<R>(own, ia), nbi = ld4<R>(nbs, ia);
-        const V3<R> sj = ld4<R>(own, ja), nbj = ld4<R>(nbs, ja);
-        const Rand4 rn = philox(sweep, k, 2u + (uint32_t)C, a.inst, a.key0, a.key1);
-        const V3<R> ti = cone_move(si, Prim<R>::u01(rn.r0), Prim<R>::u01(rn.r1), c1);
+    for (uint32_t ia = blockIdx.x * kThreads + threadIdx.x; ia < a.Nc; ia += gridDim.x * kThreads) {
+        const uint32_t pos = unshuffle_index(ia, a.Nc, half, mask, key);
+        if ((pos & 1u) == 0u) {
+            const uint32_t k = pos >> 1;
+            const uint32_t ja = shuffle_index(pos + 1u, a.Nc, half, mask, key);
+            const V3<R> si = ld4<R>(own, ia), nbi = ld4<R>(nbs, ia);
+            const V3<R> sj = ld4<R>(own, ja), nbj = ld4<R>(nbs, ja);
+            const Rand4 rn = philox(sweep, k, 2u + (uint32_t)C, a.inst, a.key0, a.key1);
+            const V3<R> ti = cone_move(si, Prim<R>::u01(rn.r0), Prim<R>::u01(rn.r1), c1);
 
-        // compensation of the transverse change, along/perpendicular to eC
-        const R pi_old = dot(si, ec), pi_new = dot(ti, ec), pj_old = dot(sj, ec);
-        V3<R> pj;
-        pj.x = (sj.x - pj_old * ec.x) + (si.x - pi_old * ec.x) - (ti.x - pi_new * ec.x);
-        pj.y = (sj.y - pj_old * ec.y) + (si.y - pi_old * ec.y) - (ti.y - pi_new * ec.y);
-        pj.z = (sj.z - pj_old * ec.z) + (si.z - pi_old * ec.z) - (ti.z - pi_new * ec.z);
-        const R q = dot(sj, sj) - dot(pj, pj);
-        bool ok = q > R(0);
-        const R pj_new = (pj_old >= R(0) ? R(1) : R(-1)) * Prim<R>::sqrt_(ok ? q : R(1));
-        const V3<R> tj{pj.x + pj_new * ec.x, pj.y + pj_new * ec.y, pj.z + pj_new * ec.z};
-        // (M_L'/M_L)^2 with M_L' = |M_L| + change along eC
-        const R xr = ((pi_new + pj_new) - pi_old - pj_old) * invML;
-        ok = ok && (R(1) + xr > R(0)) && (ML != 0.0);
-        const V3<R> hi{m.J * nbi.x + m.h.x, m.J * nbi.y + m.h.y, m.J * nbi.z + m.h.z};
-        const V3<R> hj{m.J * nbj.x + m.h.x, m.J * nbj.y + m.h.y, m.J * nbj.z + m.h.z};
-        const R dE = delta_e(m, si, ti, hi) + delta_e(m, sj, tj, hj);
-        const R ratio = (R(1) + xr) * (R(1) + xr) * fabs(pj_old / pj_new);
-        ok = ok && (Prim<R>::u01(rn.r2) < ratio * Prim<R>::boltzmann(dE, scale));
-        const V3<R> fi = ok ? ti : si;
-        const V3<R> fj = ok ? tj : sj;
-        if (ok) {
-            st4<R>(own, ia, ti);
-            st4<R>(own, ja, tj);
-            nacc = 2;
-        }
-        if (OBS) {
-            acc.ex += (double)(-m.J * dot(fi, nbi)) + (double)(-m.J * dot(fj, nbj));
-            add_site<R, true>(acc, m, fi);
-            add_site<R, true>(acc, m, fj);
+            // compensation of the transverse change, along/perpendicular to eC
+            const R pi_old = dot(si, ec), pi_new = dot(ti, ec), pj_old = dot(sj, ec);
+            V3<R> pj;
+            pj.x = (sj.x - pj_old * ec.x) + (si.x - pi_old * ec.x) - (ti.x - pi_new * ec.x);
+            pj.y = (sj.y - pj_old * ec.y) + (si.y - pi_old * ec.y) - (ti.y - pi_new * ec.y);
+            pj.z = (sj.z - pj_old * ec.z) + (si.z - pi_old * ec.z) - (ti.z - pi_new * ec.z);
+            const R q = dot(sj, sj) - dot(pj, pj);
+            bool ok = q > R(0);
+            const R pj_new = (pj_old >= R(0) ? R(1) : R(-1)) * Prim<R>::sqrt_(ok ? q : R(1));
+            const V3<R> tj{pj.x + pj_new * ec.x, pj.y + pj_new * ec.y, pj.z + pj_new * ec.z};
+            // (M_L'/M_L)^2 with M_L' = |M_L| + change along eC
+            const R xr = ((pi_new + pj_new) - pi_old - pj_old) * invML;
+            ok = ok && (R(1) + xr > R(0)) && (ML != 0.0);
+            const V3<R> hi{m.J * nbi.x + m.h.x, m.J * nbi.y + m.h.y, m.J * nbi.z + m.h.z};
+            const V3<R> hj{m.J * nbj.x + m.h.x, m.J * nbj.y + m.h.y, m.J * nbj.z + m.h.z};
+            const R dE = delta_e(m, si, ti, hi) + delta_e(m, sj, tj, hj);
+            const R ratio = (R(1) + xr) * (R(1) + xr) * fabs(pj_old / pj_new);
+            ok = ok && (Prim<R>::u01(rn.r2) < ratio * Prim<R>::boltzmann(dE, scale));
+            const V3<R> fi = ok ? ti : si;
+            const V3<R> fj = ok ? tj : sj;
+            if (ok) {
+                st4<R>(own, ia, ti);
+                st4<R>(own, ja, tj);
+                nacc += 2;
+            }
+            if (OBS) {
+                acc.ex += (double)(-m.J * dot(fi, nbi)) + (double)(-m.J * dot(fj, nbj));
+                add_site<R, true>(acc, m, fi);
+                add_site<R, true>(acc, m, fj);
+            }
         }
     }
     KArgs<R> ra = a;
@@ -392,14 +394,15 @@ static void constrained_go(const DevLattice& d, int step, const double eC[3], do
     Vec4<R>* aos = static_cast<Vec4<R>*>(d.aos);
     Vec4<R>* nbs = static_cast<Vec4<R>*>(d.nbs);
     const uint32_t n = (uint32_t)d.Nc;
-    const uint32_t grid = cdiv(n, kThreads);
+    const uint32_t full = cdiv(n, kThreads);
+    const uint32_t grid = full < (uint32_t)kGatherBlocks ? full : (uint32_t)kGatherBlocks;
     *blocks = grid;
     if (step == kAosIn) {
-        aos_copy_kernel<R, true><<<dim3(grid, 2), kThreads, 0, s>>>(a, aos);
+        aos_copy_kernel<R, true><<<dim3(full, 2), kThreads, 0, s>>>(a, aos);
         return;
     }
     if (step == kAosOut) {
-        aos_copy_kernel<R, false><<<dim3(grid, 2), kThreads, 0, s>>>(a, aos);
+        aos_copy_kernel<R, false><<<dim3(full, 2), kThreads, 0, s>>>(a, aos);
         return;
     }
     if (step == kNbRed) {

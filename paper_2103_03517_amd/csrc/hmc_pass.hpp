@@ -285,20 +285,55 @@ __device__ __forceinline__ void finalize_body(DevState* st, const double* part, 
 #pragma unroll
     for (int i = 0; i <= kNumPart; ++i) v[i] = 0.0;
     if (fin & kFinCounts) {
+        // integer sums: any order gives the same total; four loads in flight
         unsigned long long c = 0;
-        for (uint32_t i = t; i < nred; i += kThreads) c += cnt[i];
-        for (uint32_t i = t; i < nblack; i += kThreads) c += cnt[cnt_stride + i];
+        for (uint32_t i = t; i < nred; i += 4 * kThreads) {
+            uint32_t w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t j = i + (uint32_t)u * kThreads;
+                const uint32_t x = cnt[j < nred ? j : i];     // always in range
+                w[u] = j < nred ? x : 0u;
+            }
+            c += (unsigned long long)w[0] + w[1] + w[2] + w[3];
+        }
+        for (uint32_t i = t; i < nblack; i += 4 * kThreads) {
+            uint32_t w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t j = i + (uint32_t)u * kThreads;
+                const uint32_t x = cnt[cnt_stride + (j < nblack ? j : i)];
+                w[u] = j < nblack ? x : 0u;
+            }
+            c += (unsigned long long)w[0] + w[1] + w[2] + w[3];
+        }
         v[kNumPart] = (double)c;
     }
     if (fin & kFinObs) {
-        // each thread takes whole 96-byte records: six independent 16-byte loads
-        for (uint32_t i = t; i < npart; i += kThreads) {
-            const double2* p = reinterpret_cast<const double2*>(part + (size_t)i * kNumPart);
+        // each thread takes whole 96-byte records t, t + 256, t + 512, ...:
+        // the loads of four records are issued together (the loop is bound by
+        // their latency), then added in record order, so the sums are those
+        // of a plain record-by-record loop
+        // (a record past the end is read at i0 and added as +0.0, which
+        // leaves every sum unchanged, so there is no branch in the loop)
+        constexpr int U = 4;
+        for (uint32_t i0 = t; i0 < npart; i0 += U * kThreads) {
+            double2 q[U][kNumPart / 2];
 #pragma unroll
-            for (int k = 0; k < kNumPart / 2; ++k) {
-                const double2 q = p[k];
-                v[2 * k] += q.x;
-                v[2 * k + 1] += q.y;
+            for (int u = 0; u < U; ++u) {
+                const uint32_t i = i0 + (uint32_t)u * kThreads;
+                const double2* p = reinterpret_cast<const double2*>(part + (size_t)(i < npart ? i : i0) * kNumPart);
+#pragma unroll
+                for (int k = 0; k < kNumPart / 2; ++k) q[u][k] = p[k];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool in = i0 + (uint32_t)u * kThreads < npart;
+#pragma unroll
+                for (int k = 0; k < kNumPart / 2; ++k) {
+                    v[2 * k] += in ? q[u][k].x : 0.0;
+                    v[2 * k + 1] += in ? q[u][k].y : 0.0;
+                }
             }
         }
     }

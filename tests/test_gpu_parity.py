@@ -247,6 +247,28 @@ def test_plane_means(H):
     assert np.allclose(h.plane_means(), S.mean(axis=(1, 2)), rtol=0, atol=1e-12)
 
 
+def test_constrained_fp64_grid_stride_size(H, O):
+    """Above 2^20 spins the constrained kernels loop over their sites (at
+    most 2048 work-groups): 128 x 128 x 68 FP64 against the reference for
+    two sampled sweeps."""
+    _say("constrained grid-stride 128x128x68")
+    shape = (128, 128, 68)
+    eC = np.array([0.2, -0.3, 0.9])
+    eC /= np.linalg.norm(eC)
+    kw = dict(J=1.0, Ku=0.02, Kc=0.03, eu=(0, 0, 1), seed=17, instance=2)
+    n = shape[0] * shape[1] * shape[2]
+    S = inputs.tilted_spins(n, 9, spread=0.3, axis=eC)
+    g, o = _pair(H, O, shape, kw, spins=S)
+    for _ in range(2):
+        acc_g = g.constrained_sweep(0.8, eC, sample=True)
+        acc_o = o.constrained_sweep(0.8, eC, sample=True)
+        assert g.observables()["accepted_last"] == acc_o
+        assert np.max(np.abs(g.spins() - o.spins())) <= TOL
+    a, b = g.observables(), o.observables(0.8)
+    assert np.allclose(a["mean_torque"], b["mean_torque"], rtol=1e-9, atol=1e-12)
+    assert np.allclose(a["mean_E"], b["mean_E"], rtol=1e-11, atol=1e-13)
+
+
 def test_mixed_standard_and_constrained(H, O):
     """Standard and constrained sweeps share the sweep counter and cone angle;
     the constrained pass takes M_L from the current spins after a standard one."""
