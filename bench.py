@@ -212,6 +212,7 @@ def serve_leg(rate=20.0, seconds=10.0):
             "p50_latency_s": live["p50_s"], "p99_latency_s": live["p99_s"], "max_latency_s": live["max_s"],
             "jobs_per_s": live["jobs_per_s"], "max_active": srv.stats["max_active"],
             "ticks": srv.stats["ticks"], "batch_rebuilds": srv.stats["rebuilds"],
+            "host_phase_s": {k: round(v, 3) for k, v in srv.phase_s.items()},
             "saturation_jobs_per_s": cap["jobs_per_s"], "saturation_updates_per_s": cap["updates_per_s"],
             "saturation_p99_latency_s": cap["p99_s"]}
 

@@ -74,7 +74,10 @@ typedef struct {
     double   h[3];          /* Zeeman field mu0*mu_S*H_a in energy units */
     uint64_t seed;          /* Philox key */
     uint32_t instance;      /* fourth Philox counter word */
-    int32_t  init;          /* 0: every spin along init_dir; 1: uniform on the sphere */
+    int32_t  init;          /* 0: every spin along init_dir; 1: uniform on the sphere;
+                               2: one domain wall across z (for boundary_z = 1): the
+                               T = 0 profile S = (sech u, 0, -tanh u), u = pi (z - z0) /
+                               init_width, centred between planes nz/2 - 1 and nz/2 */
     double   init_dir[3];   /* non-zero when init == 0 */
     int32_t  theta0_deg;    /* initial cone angle, 1..180 degrees */
     int32_t  boundary_z;    /* 0: periodic along z; 1: anti-periodic along z (the
@@ -86,6 +89,7 @@ typedef struct {
     int32_t  bond_masks;    /* 1: keep a per-site mask of active bonds (set with
                                hmc_set_bond_masks; every bond active until then),
                                1 byte per spin more in the workspace; 0: none */
+    double   init_width;    /* wall width of init = 2 (sites, > 0) */
 } hmc_params;
 
 /* Observables.  The instantaneous values describe the spins at the time of
@@ -257,6 +261,14 @@ size_t hmc_batch_workspace_bytes(int32_t count);
  * masks), HMC_ENOMEM (workspace too small or misaligned), HMC_EHIP. */
 int hmc_batch_create(hmc_lattice* const* lattices, int32_t count, void* dev_ws, size_t ws_bytes,
                      hmc_batch** out);
+
+/* Replaces the lattices of a batch with lattices[0 .. count-1] (same rules
+ * as hmc_batch_create), reusing its workspace, staging buffer and stream:
+ * count may be at most the capacity of the workspace given at creation
+ * (the largest n with hmc_batch_workspace_bytes(n) <= ws_bytes).  The new
+ * table is uploaded on the stream; graphs are captured again when next
+ * needed.  Errors: HMC_EINVAL, HMC_ENOMEM (above the capacity), HMC_EHIP. */
+int hmc_batch_set_lattices(hmc_batch* B, hmc_lattice* const* lattices, int32_t count);
 
 /* Enqueues n_sweeps standard sweeps (Table A1) of every lattice of the
  * batch, lattice i at temperature T[i] (count values, each > 0 and

@@ -30,6 +30,7 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32),
         ("init", ctypes.c_int32), ("init_dir", ctypes.c_double * 3),
         ("theta0_deg", ctypes.c_int32), ("boundary_z", ctypes.c_int32), ("bond_masks", ctypes.c_int32),
+        ("init_width", ctypes.c_double),
     ]
 
 
@@ -63,7 +64,8 @@ SYMBOLS = ("hmc_workspace_bytes", "hmc_init_lattice", "hmc_sweep", "hmc_constrai
            "hmc_last_error", "hmc_batch_workspace_bytes", "hmc_batch_create", "hmc_batch_sweep",
            "hmc_batch_tune", "hmc_batch_set_graph", "hmc_batch_set_timing",
            "hmc_batch_read_timing", "hmc_batch_destroy", "hmc_batch_last_error",
-           "hmc_batch_observables", "hmc_batch_reset_stats", "hmc_batch_sweep_each")
+           "hmc_batch_observables", "hmc_batch_reset_stats", "hmc_batch_sweep_each",
+           "hmc_batch_set_lattices")
 
 _lib = None
 
@@ -140,6 +142,8 @@ def lib():
     L.hmc_batch_reset_stats.argtypes = [vp]
     L.hmc_batch_sweep_each.restype = i32
     L.hmc_batch_sweep_each.argtypes = [vp, P(dbl), P(i32), i32]
+    L.hmc_batch_set_lattices.restype = i32
+    L.hmc_batch_set_lattices.argtypes = [vp, P(vp), i32]
     _lib = L
     return L
 
@@ -152,7 +156,7 @@ class HmcError(RuntimeError):
 
 def make_params(nx, ny, nz, precision=64, J=1.0, Ku=0.0, eu=(0.0, 0.0, 1.0), Kc=0.0,
                 h=(0.0, 0.0, 0.0), seed=1, instance=0, init="aligned", init_dir=(0.0, 0.0, 1.0),
-                theta0_deg=30, boundary_z="periodic", bond_masks=False):
+                theta0_deg=30, boundary_z="periodic", bond_masks=False, init_width=0.0):
     p = Params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.precision = int(precision)
@@ -161,7 +165,8 @@ def make_params(nx, ny, nz, precision=64, J=1.0, Ku=0.0, eu=(0.0, 0.0, 1.0), Kc=
     p.h[:] = [float(v) for v in h]
     p.seed = int(seed)
     p.instance = int(instance)
-    p.init = {"aligned": 0, "random": 1}[init] if isinstance(init, str) else int(init)
+    p.init = {"aligned": 0, "random": 1, "wall": 2}[init] if isinstance(init, str) else int(init)
+    p.init_width = float(init_width)
     p.init_dir[:] = [float(v) for v in init_dir]
     p.theta0_deg = int(theta0_deg)
     p.boundary_z = ({"periodic": 0, "antiperiodic": 1, "open": 2}[boundary_z] if isinstance(boundary_z, str)
@@ -305,11 +310,11 @@ class Batch:
     lattices stay usable on their own (observables, checkpoints, single
     sweeps) and must outlive the batch."""
 
-    def __init__(self, lattices):
+    def __init__(self, lattices, capacity=None):
         self._lib = lib()
         self.lattices = list(lattices)
         n = len(self.lattices)
-        nbytes = int(self._lib.hmc_batch_workspace_bytes(n))
+        nbytes = int(self._lib.hmc_batch_workspace_bytes(max(n, int(capacity or 0))))
         handles = (ctypes.c_void_p * max(n, 1))(*[l._h for l in self.lattices])
         dev = self.lattices[0].device if n else torch.device("cuda")
         self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
@@ -338,6 +343,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def set_lattices(self, lattices):
+        """Swap in another list of lattices (up to the capacity given at creation)."""
+        new = list(lattices)
+        handles = (ctypes.c_void_p * max(len(new), 1))(*[l._h for l in new])
+        self._check(self._lib.hmc_batch_set_lattices(self._h, handles, len(new)))
+        self.lattices = new
 
     def sweep(self, T, n=1, sample=False):
         """n standard sweeps of every lattice; T is one value or one per lattice."""

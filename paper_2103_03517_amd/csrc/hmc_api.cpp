@@ -128,7 +128,11 @@ int validate(const hmc_params* p, char* msg, size_t n)
         return HMC_EINVAL;
     }
     if (!nonzero3(p->eu)) { snprintf(msg, n, "uniaxial axis eu must be non-zero"); return HMC_EINVAL; }
-    if (p->init != 0 && p->init != 1) { snprintf(msg, n, "init must be 0 or 1"); return HMC_EINVAL; }
+    if (p->init < 0 || p->init > 2) { snprintf(msg, n, "init must be 0, 1 or 2"); return HMC_EINVAL; }
+    if (p->init == 2 && !(p->init_width > 0.0 && isfinite(p->init_width))) {
+        snprintf(msg, n, "init = 2 needs a positive, finite init_width");
+        return HMC_EINVAL;
+    }
     if (p->init == 0 && (!finite3(p->init_dir) || !nonzero3(p->init_dir))) {
         snprintf(msg, n, "init_dir must be finite and non-zero");
         return HMC_EINVAL;
@@ -292,6 +296,7 @@ int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes, void* h
     d.key1 = (uint32_t)(p->seed >> 32);
     d.instance = p->instance;
     d.init_mode = p->init;
+    d.init_width = p->init_width;
     d.zbound = p->boundary_z;
     d.mask = p->bond_masks ? reinterpret_cast<uint8_t*>(base + lay.off_mask) : nullptr;
 

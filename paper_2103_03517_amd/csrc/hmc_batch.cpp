@@ -60,6 +60,7 @@ BatchLayout batch_layout(int32_t count, int precision)
 
 struct hmc_batch {
     std::vector<hmc_lattice*> lat;
+    int32_t capacity = 0;      // most lattices the workspace and staging hold
     int precision = 32;
     hipStream_t stream = nullptr;
     char* ws = nullptr;
@@ -96,6 +97,8 @@ int bfail(hmc_batch* B, int status, const char* what, hipError_t e = hipSuccess)
 
 void drop_graphs(hmc_batch* B)
 {
+    // a replay may still be running on the stream
+    if (B->exec[0] || B->exec[1]) (void)hipStreamSynchronize(B->stream);
     for (auto& g : B->exec)
         if (g) {
             (void)hipGraphExecDestroy(g);
@@ -262,6 +265,22 @@ void destroy_batch(hmc_batch* B)
     delete B;
 }
 
+// The checks shared by hmc_batch_create and hmc_batch_set_lattices.
+int check_lattices(hmc_lattice* const* lattices, int32_t count)
+{
+    if (!lattices || count < 1 || count > kMaxBatch) return HMC_EINVAL;
+    // lattices with bond masks run the masked pass, which batches do not have
+    for (int32_t i = 0; i < count; ++i)
+        if (!lattices[i] || lattices[i]->d.mask) return HMC_EINVAL;
+    std::vector<hmc_lattice*> sorted(lattices, lattices + count);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return HMC_EINVAL;
+    for (int32_t i = 1; i < count; ++i)
+        if (lattices[i]->d.precision != lattices[0]->d.precision || lattices[i]->stream != lattices[0]->stream)
+            return HMC_EINVAL;
+    return HMC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -276,37 +295,39 @@ int hmc_batch_create(hmc_lattice* const* lattices, int32_t count, void* dev_ws, 
 {
     if (!out) return HMC_EINVAL;
     *out = nullptr;
-    if (!lattices || count < 1 || count > kMaxBatch) return HMC_EINVAL;
-    // lattices with bond masks run the masked pass, which batches do not have
-    for (int32_t i = 0; i < count; ++i)
-        if (!lattices[i] || lattices[i]->d.mask) return HMC_EINVAL;
-    std::vector<hmc_lattice*> sorted(lattices, lattices + count);
-    std::sort(sorted.begin(), sorted.end());
-    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return HMC_EINVAL;
-    for (int32_t i = 1; i < count; ++i)
-        if (lattices[i]->d.precision != lattices[0]->d.precision || lattices[i]->stream != lattices[0]->stream)
-            return HMC_EINVAL;
+    int st = check_lattices(lattices, count);
+    if (st != HMC_OK) return st;
     const BatchLayout lay = batch_layout(count, lattices[0]->d.precision);
     if (!dev_ws || ws_bytes < hmc_batch_workspace_bytes(count) || ((uintptr_t)dev_ws % kAlign) != 0)
         return HMC_ENOMEM;
+    // capacity: the most lattices this workspace holds (sizes grow with the count)
+    int32_t lo = count, hi = kMaxBatch;
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo + 1) / 2;
+        if (hmc_batch_workspace_bytes(mid) <= ws_bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    const int32_t capacity = lo;
+    const size_t staging_bytes = batch_layout(capacity, 64).total;
 
     hmc_batch* B = new (std::nothrow) hmc_batch();
     if (!B) return HMC_ENOMEM;
     B->lat.assign(lattices, lattices + count);
+    B->capacity = capacity;
     B->precision = lattices[0]->d.precision;
     B->stream = lattices[0]->stream;
     B->ws = static_cast<char*>(dev_ws);
     B->lay = lay;
     B->shape.assign(count, {0, 0});
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&B->staging), lay.total, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&B->staging), staging_bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&B->upload_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(B->upload_done, B->stream);
     if (e != hipSuccess) {
         destroy_batch(B);
         return HMC_EHIP;
     }
-    memset(B->staging, 0, lay.total);
-    int st = refresh_table(B);
+    memset(B->staging, 0, staging_bytes);
+    st = refresh_table(B);
     if (st == HMC_OK) {
         e = hipStreamSynchronize(B->stream);
         if (e != hipSuccess) st = HMC_EHIP;
@@ -458,6 +479,27 @@ int hmc_batch_tune(hmc_batch* B, const double* T, int32_t trial_sweeps)
         if (e != hipSuccess) st = bfail(B, HMC_EHIP, "hipStreamSynchronize", e);
     }
     return st;
+}
+
+int hmc_batch_set_lattices(hmc_batch* B, hmc_lattice* const* lattices, int32_t count)
+{
+    if (!B) return HMC_EINVAL;
+    int st = check_lattices(lattices, count);
+    if (st != HMC_OK) return bfail(B, st, "invalid lattice list (null, duplicate, masked or mixed)");
+    if (lattices[0]->d.precision != B->precision || lattices[0]->stream != B->stream)
+        return bfail(B, HMC_EINVAL, "the lattices must keep the batch's precision and stream");
+    if (count > B->capacity) return bfail(B, HMC_ENOMEM, "more lattices than the workspace holds");
+    hipError_t e = staging_wait(B);
+    if (e != hipSuccess) return bfail(B, HMC_EHIP, "waiting for the staging buffer", e);
+    drop_graphs(B);
+    B->lat.assign(lattices, lattices + count);
+    B->lay = batch_layout(count, B->precision);
+    B->shape.assign(count, {0, 0});
+    B->table_valid = false;
+    B->call_valid = false;
+    B->T_last.clear();
+    B->fin_last.clear();
+    return refresh_table(B);
 }
 
 int hmc_batch_observables(hmc_batch* B, hmc_obs* out)

@@ -70,8 +70,9 @@ struct DevLattice {
     int64_t max_blocks;
     double J, Ku, eu[3], Kc, h[3];
     uint32_t key0, key1, instance;
-    int32_t init_mode;
+    int32_t init_mode;        // 0 aligned, 1 uniform random, 2 wall across z
     double init_dir[3];
+    double init_width;        // wall width of init_mode 2
     int32_t zbound;           // z boundary: 0 periodic, 1 anti-periodic, 2 open
     uint8_t* mask;            // [colour][Nc] active-bond bits, or null (every bond)
 };

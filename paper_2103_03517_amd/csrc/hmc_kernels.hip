@@ -37,12 +37,19 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(DevState* st, const 
 // tag 4 (z = 2 u0 - 1, azimuth 2 pi u1).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(kThreads) void init_kernel(const KArgs<R> a, int mode, R d0, R d1, R d2)
+__global__ __launch_bounds__(kThreads) void init_kernel(const KArgs<R> a, int mode, R d0, R d1, R d2,
+                                                       double width)
 {
     const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
     const int c = blockIdx.y;
     if (k >= a.Nc) return;
     V3<R> s{d0, d1, d2};
+    if (mode == 2) {
+        // one wall across z: the T = 0 profile (sech u, 0, -tanh u)
+        const uint32_t z = k / a.P;
+        const double u = M_PI * ((double)z - (0.5 * (double)a.nz - 0.5)) / width;
+        s = V3<R>{(R)(1.0 / cosh(u)), R(0), (R)(-tanh(u))};
+    }
     if (mode == 1) {
         const uint32_t r = k / a.hx;
         const uint32_t y = r % a.ny, z = r / a.ny;
@@ -370,10 +377,11 @@ hipError_t launch_init(const DevLattice& d, hipStream_t s)
     if (d.precision == 32) {
         auto a = make_args<float>(d);
         init_kernel<float><<<grid, kThreads, 0, s>>>(a, d.init_mode, (float)d.init_dir[0], (float)d.init_dir[1],
-                                                     (float)d.init_dir[2]);
+                                                     (float)d.init_dir[2], d.init_width);
     } else {
         auto a = make_args<double>(d);
-        init_kernel<double><<<grid, kThreads, 0, s>>>(a, d.init_mode, d.init_dir[0], d.init_dir[1], d.init_dir[2]);
+        init_kernel<double><<<grid, kThreads, 0, s>>>(a, d.init_mode, d.init_dir[0], d.init_dir[1], d.init_dir[2],
+                                                      d.init_width);
     }
     return hipGetLastError();
 }

@@ -289,8 +289,7 @@ def wall_run(temps, shape=(64, 64, 512), precision=32, J=1.0, Ku=0.01, equil=500
     lats = []
     for i, T in enumerate(temps):
         g = Lattice(nx, ny, nz, precision=precision, J=J, Ku=Ku, eu=(0.0, 0.0, 1.0), seed=seed, instance=i,
-                    init="aligned", boundary_z="antiperiodic")
-        g.set_spins(Wm.initial_wall(nx, ny, nz, width=Wm.zero_temperature_width(J, Ku)))
+                    init="wall", init_width=Wm.zero_temperature_width(J, Ku), boundary_z="antiperiodic")
         lats.append(g)
     B = Batch(lats)
     B.sweep(list(temps), equil)

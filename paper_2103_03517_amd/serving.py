@@ -121,6 +121,9 @@ class Server:
         self.graph = int(graph)
         self.log = log
         self.stats = {"ticks": 0, "rebuilds": 0, "max_active": 0, "max_bytes": 0, "sweep_launches": 0}
+        # host seconds per phase of the loop (the device waits during admit,
+        # rebuild and retire, which follow a synchronising read)
+        self.phase_s = {"admit": 0.0, "rebuild": 0.0, "enqueue": 0.0, "read": 0.0, "retire": 0.0}
 
     def need_bytes(self, job):
         return workspace_bytes(job.params(self.precision))
@@ -139,33 +142,46 @@ class Server:
         return dict(self.shapes)
 
     def _admit(self, job, now):
-        job.lattice = Lattice(*job.shape, precision=self.precision, J=job.J, Ku=job.Ku, eu=(0.0, 0.0, 1.0),
-                              seed=job.seed, instance=job.instance, init="aligned",
-                              boundary_z="antiperiodic" if job.kind == "wall" else "periodic")
         if job.kind == "wall":
-            job.lattice.set_spins(W.initial_wall(*job.shape, width=W.zero_temperature_width(job.J, job.Ku)))
+            # the T = 0 wall profile, written on the device
+            job.lattice = Lattice(*job.shape, precision=self.precision, J=job.J, Ku=job.Ku, eu=(0.0, 0.0, 1.0),
+                                  seed=job.seed, instance=job.instance, init="wall",
+                                  init_width=W.zero_temperature_width(job.J, job.Ku), boundary_z="antiperiodic")
+        else:
+            job.lattice = Lattice(*job.shape, precision=self.precision, J=job.J, Ku=job.Ku, eu=(0.0, 0.0, 1.0),
+                                  seed=job.seed, instance=job.instance, init="aligned")
         if job.shape in self.shapes:
             job.lattice.set_launch(*self.shapes[job.shape])
         job.admitted = now
         job.bytes = self.need_bytes(job)
 
-    def _retire(self, job, now):
+    @staticmethod
+    def _fit_walls(job):
+        fits = []
+        for prof in job.profiles:
+            try:
+                fits.append(W.fit_wall(prof, delta_guess=W.zero_temperature_width(job.J, job.Ku)))
+            except RuntimeError:
+                pass
+        if fits:
+            f = np.array(fits)
+            job.result.update(delta=float(f[:, 2].mean()), m_wall=float(f[:, 0].mean()), wall_fits=len(f))
+
+    def _retire(self, job, now, pool, clock):
         job.result = block_stats_from_reads(job.reads, job.lattice.n, job.T)
         job.result.update(edge=job.edge, shape=list(job.shape), kind=job.kind,
                           sweeps=job.reads[-1]["sweeps_done"], theta_deg=job.reads[-1]["theta_deg"])
-        if job.kind == "wall":
-            fits = []
-            for prof in job.profiles:
-                try:
-                    fits.append(W.fit_wall(prof, delta_guess=W.zero_temperature_width(job.J, job.Ku)))
-                except RuntimeError:
-                    pass
-            if fits:
-                f = np.array(fits)
-                job.result.update(delta=float(f[:, 2].mean()), m_wall=float(f[:, 0].mean()), wall_fits=len(f))
-        job.finished = now
         job.lattice.close()
         job.lattice = None
+        if job.kind == "wall":
+            # the profile fits run beside the loop (the main thread mostly
+            # waits on the device); the job finishes when its fits are done
+            def work(j=job):
+                self._fit_walls(j)
+                j.finished = clock()
+            return pool.submit(work)
+        job.finished = now
+        return None
 
     def run(self, jobs, realtime=True):
         """Serves `jobs` (arrival times in seconds from the start).  With
@@ -189,17 +205,22 @@ class Server:
         def clock():
             return time.perf_counter() - t0
 
+        from concurrent.futures import ThreadPoolExecutor
+        pool = ThreadPoolExecutor(max_workers=2)
+        futures = []
         done = []
         while pending or waiting or active:
             now = clock()
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
+            t_ph = time.perf_counter()
             while waiting and len(active) < self.max_slots and used + self.need_bytes(waiting[0]) <= self.hbm_budget:
                 j = waiting.popleft()
                 self._admit(j, clock())
                 used += j.bytes
                 active.append(j)
                 changed = True
+            self.phase_s["admit"] += time.perf_counter() - t_ph
             self.stats["max_active"] = max(self.stats["max_active"], len(active))
             self.stats["max_bytes"] = max(self.stats["max_bytes"], used)
             if not active:
@@ -207,21 +228,28 @@ class Server:
                     time.sleep(max(0.0, pending[0].arrival - clock()))
                 continue
             if changed:
-                if batch is not None:
-                    batch.close()
-                batch = Batch([j.lattice for j in active])
-                if self.graph:
-                    batch.set_graph(self.graph)
+                t_ph = time.perf_counter()
+                if batch is None:
+                    # one batch for the whole run, sized for max_slots lattices
+                    batch = Batch([j.lattice for j in active], capacity=self.max_slots)
+                    if self.graph:
+                        batch.set_graph(self.graph)
+                else:
+                    batch.set_lattices([j.lattice for j in active])
                 self.stats["rebuilds"] += 1
                 changed = False
+                self.phase_s["rebuild"] += time.perf_counter() - t_ph
             q = min(self.quantum, min(j.next_event() for j in active))
+            t_ph = time.perf_counter()
             batch.sweep_each([j.T for j in active], [j.sampling() for j in active], q)
+            self.phase_s["enqueue"] += time.perf_counter() - t_ph
             self.stats["ticks"] += 1
             self.stats["sweep_launches"] += q
             for j in active:
                 j.done += q
             at_block_end = [j.sampling() and j.done > j.equil and (j.done - j.equil) % j.block == 0
                             for j in active]
+            t_ph = time.perf_counter()
             if any(at_block_end):
                 obs = batch.observables()
                 for j, o, hit in zip(active, obs, at_block_end):
@@ -229,11 +257,15 @@ class Server:
                         j.reads.append(o)
                         if j.kind == "wall":
                             j.profiles.append(j.lattice.plane_means()[:, 2])
+            self.phase_s["read"] += time.perf_counter() - t_ph
             finished = [j for j in active if j.done >= j.total]
+            t_ph = time.perf_counter()
             if finished:
                 now = clock()
                 for j in finished:
-                    self._retire(j, now)
+                    f = self._retire(j, now, pool, clock)
+                    if f is not None:
+                        futures.append(f)
                     used -= j.bytes
                     done.append(j)
                 active = [j for j in active if j.done < j.total]
@@ -241,8 +273,12 @@ class Server:
                 if self.log:
                     self.log(f"t={now:.3f}s retired {len(finished)}, active {len(active)}, "
                              f"waiting {len(waiting)}, pending {len(pending)}")
+            self.phase_s["retire"] += time.perf_counter() - t_ph
         if batch is not None:
             batch.close()
+        for f in futures:
+            f.result()
+        pool.shutdown()
         torch.cuda.synchronize()
         return done
 

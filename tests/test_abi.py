@@ -44,7 +44,8 @@ def test_strerror(hmc):
     (dict(nx=3), -2), (dict(ny=0), -2), (dict(nz=5), -2), (dict(nx=2048), -2),
     (dict(precision=16), -1), (dict(J=float("nan")), -1), (dict(eu=(0, 0, 0)), -1),
     (dict(h=(0, float("inf"), 0)), -1), (dict(theta0_deg=0), -1), (dict(theta0_deg=181), -1),
-    (dict(init=2), -1), (dict(init_dir=(0, 0, 0)), -1), (dict(boundary_z=3), -1),
+    (dict(init=3), -1), (dict(init=2), -1), (dict(init=2, init_width=float("nan")), -1),
+    (dict(init_dir=(0, 0, 0)), -1), (dict(boundary_z=3), -1),
     (dict(boundary_z=-1), -1), (dict(nz=5, boundary_z=1), -2),
     (dict(nz=0, boundary_z=2), -2),
 ])
@@ -129,5 +130,6 @@ def test_batch_host_checks(hmc):
     assert L.hmc_batch_observables(None, None) == -1
     assert L.hmc_batch_reset_stats(None) == -1
     assert L.hmc_batch_sweep_each(None, T, None, 1) == -1
+    assert L.hmc_batch_set_lattices(None, None, 1) == -1
     L.hmc_batch_destroy(None)
     assert L.hmc_batch_last_error(None) == b"no batch"

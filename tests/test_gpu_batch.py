@@ -204,6 +204,37 @@ def test_launch_change_and_mixed_use(H):
         assert a.get_state() == b.get_state()
 
 
+def test_set_lattices_reuses_the_batch(H):
+    """Swapping lattices in and out of one batch (up to its capacity) gives
+    the results of sweeping them alone."""
+    T = _temps(len(MIX), seed=12)
+    alone = _make(H, 32, seed0=200)
+    inb = _make(H, 32, seed0=200)
+    B = H.Batch(inb[:2], capacity=5)
+    B.sweep(T[:2], 3)
+    B.set_lattices([inb[2], inb[0], inb[5], inb[6]])
+    B.sweep([T[2], T[0], T[5], T[6]], 4, sample=True)
+    B.set_lattices([inb[1]])
+    B.sweep([T[1]], 2)
+    for i, n, smp in [(0, 3, False), (1, 3, False), (2, 4, True), (0, 4, True), (5, 4, True), (6, 4, True),
+                      (1, 2, False)]:
+        alone[i].sweep(T[i], n, sample=smp)
+    for i in (0, 1, 2, 5, 6):
+        assert alone[i].get_state() == inb[i].get_state(), MIX[i]
+    with pytest.raises(H.HmcError) as e:
+        B.set_lattices(inb[:6])
+    assert e.value.status == H.ENOMEM
+    B.close()
+
+
+def test_wall_initial_state(H):
+    """init = "wall" writes the T = 0 profile on the device."""
+    from paper_2103_03517_amd import walls as W
+    shape, w = (4, 6, 40), 9.5
+    g = H.Lattice(*shape, precision=64, init="wall", init_width=w, boundary_z="antiperiodic")
+    assert np.allclose(g.spins(), W.initial_wall(*shape, width=w), rtol=0, atol=1e-14)
+
+
 def test_batch_argument_errors(H):
     import ctypes
     g32 = H.Lattice(4, 4, 4, precision=32)
