@@ -149,6 +149,7 @@ def batch_leg(sequential=False):
         "jobs": len(jobs), "spins": i32["spins"], "sweeps_per_job": 5000,
         "jobs_per_s": len(jobs) / i32["run_s"], "updates_per_s": i32["updates"] / i32["run_s"],
         "wall_s": i32["run_s"], "tune_s": i32["tune_s"], "launch_shapes": shapes,
+        "chunk_bytes": i32.get("chunk_bytes"),
         "fp64_jobs_per_s": len(jobs) / i64["run_s"], "fp64_updates_per_s": i64["updates"] / i64["run_s"],
         "precision": {"max_abs_dm": max(c["dm"] for c in cmp),
                       "jobs_within_1e-3": sum(c["dm"] <= 1e-3 for c in cmp),

@@ -293,18 +293,31 @@ int hmc_batch_observables(hmc_batch* B, hmc_obs* out);
  * one kernel on the stream and without synchronising. */
 int hmc_batch_reset_stats(hmc_batch* B);
 
-/* Autotuner: for each distinct lattice size of the batch, in turn, times
- * trial_sweeps (1 .. 1000) batch sweeps at temperatures T for every
- * admissible launch shape (sites_per_thread 1, 2, 4 within the LDS
- * budget; z_chunk 2 .. 64, powers of two up to nz) with the other sizes
- * held, and keeps the fastest.  The chosen shapes are set on the lattices
- * (hmc_get_launch reads them).  Every lattice's state is saved before and
+/* Autotuner.  Every configuration is timed as a sweep call runs it (chunk
+ * after chunk, max(trial_sweeps, 20) sweeps each, at temperatures T).  It
+ * picks the chunk size among 0 (one chunk), 96, 128, 160, 192, 224 and
+ * 256 MiB; then, for each distinct lattice size in turn (largest total
+ * first), the fastest admissible launch shape (sites_per_thread 1, 2, 4
+ * within the LDS budget; z_chunk 2 .. 64, powers of two up to nz) with the
+ * other sizes held; then the chunk size again.  trial_sweeps: 1 .. 1000.
+ * The shapes are set on the lattices (hmc_get_launch reads them), the
+ * chunk size on the batch (hmc_batch_get_chunk_bytes).  Every lattice's state is saved before and
  * restored after (host copies), so tuning leaves the chains where they
  * were.  Synchronises.  Errors: HMC_EINVAL, HMC_EHIP, HMC_ENOMEM (host). */
 int hmc_batch_tune(hmc_batch* B, const double* T, int32_t trial_sweeps);
 
+/* Chunking: a batch sweep call splits the lattices (in order) into
+ * ceil(total / bytes) chunks of about equal bytes of spins and finishes all
+ * its sweeps on one chunk before the next, so that a chunk stays in the
+ * 256 MB Infinity Cache while it is swept.  Each lattice still runs red
+ * pass, black pass and finalize for every sweep in order, so its results do
+ * not depend on the chunking.  bytes = 0 (the default): one chunk.
+ * hmc_batch_tune chooses it.  Errors: HMC_EINVAL (negative), HMC_EHIP. */
+int hmc_batch_set_chunk_bytes(hmc_batch* B, int64_t bytes);
+int hmc_batch_get_chunk_bytes(const hmc_batch* B, int64_t* bytes);
+
 /* Graph replay: with sweeps_per_graph > 0, runs of that many sweeps are
- * captured once (per sample flag) as a HIP graph on a private stream and
+ * captured once (per chunk and sample flag) as a HIP graph on a private stream and
  * replayed on the lattices' stream, which removes the per-launch host
  * cost; sweeps_per_graph = 0 (the default) launches eagerly.  Replays do
  * exactly the work of the eager launches.  Timing (below) uses eager

@@ -65,7 +65,7 @@ SYMBOLS = ("hmc_workspace_bytes", "hmc_init_lattice", "hmc_sweep", "hmc_constrai
            "hmc_batch_tune", "hmc_batch_set_graph", "hmc_batch_set_timing",
            "hmc_batch_read_timing", "hmc_batch_destroy", "hmc_batch_last_error",
            "hmc_batch_observables", "hmc_batch_reset_stats", "hmc_batch_sweep_each",
-           "hmc_batch_set_lattices")
+           "hmc_batch_set_lattices", "hmc_batch_set_chunk_bytes", "hmc_batch_get_chunk_bytes")
 
 _lib = None
 
@@ -144,6 +144,10 @@ def lib():
     L.hmc_batch_sweep_each.argtypes = [vp, P(dbl), P(i32), i32]
     L.hmc_batch_set_lattices.restype = i32
     L.hmc_batch_set_lattices.argtypes = [vp, P(vp), i32]
+    L.hmc_batch_set_chunk_bytes.restype = i32
+    L.hmc_batch_set_chunk_bytes.argtypes = [vp, ctypes.c_int64]
+    L.hmc_batch_get_chunk_bytes.restype = i32
+    L.hmc_batch_get_chunk_bytes.argtypes = [vp, P(ctypes.c_int64)]
     _lib = L
     return L
 
@@ -378,6 +382,15 @@ class Batch:
     def reset_stats(self):
         """Clear every lattice's accumulators (enqueued, no synchronisation)."""
         self._check(self._lib.hmc_batch_reset_stats(self._h))
+
+    def set_chunk_bytes(self, nbytes):
+        """Sweep consecutive lattices in chunks of at most nbytes of spins (0: one chunk)."""
+        self._check(self._lib.hmc_batch_set_chunk_bytes(self._h, int(nbytes)))
+
+    def chunk_bytes(self):
+        v = ctypes.c_int64()
+        self._check(self._lib.hmc_batch_get_chunk_bytes(self._h, ctypes.byref(v)))
+        return int(v.value)
 
     def set_graph(self, sweeps_per_graph):
         self._check(self._lib.hmc_batch_set_graph(self._h, int(sweeps_per_graph)))

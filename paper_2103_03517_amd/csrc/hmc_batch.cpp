@@ -12,6 +12,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
+#include <array>
 #include <map>
 #include <new>
 #include <tuple>
@@ -24,6 +26,14 @@ namespace {
 
 constexpr int32_t kMaxBatch = 65536;
 constexpr int32_t kMaxGraphSweeps = 4096;
+// Chunk sizes the autotuner tries (bytes of spins; 0 = one chunk).  A
+// chunk is swept through all the sweeps of a call before the next one, so
+// that it stays in the 256 MB Infinity Cache; too small a chunk leaves the
+// device short of work-groups.
+constexpr size_t kChunkCandidates[] = {0, 96u << 20, 128u << 20, 160u << 20, 192u << 20, 224u << 20, 256u << 20};
+// sweeps per chunk when a chunk size is timed: the first sweep of a chunk
+// reads it from HBM, the following ones from the cache, as in a long call
+constexpr int32_t kChunkTrialSweeps = 20;
 constexpr size_t kAlign = hmc::kAlign;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -67,7 +77,14 @@ struct hmc_batch {
     BatchLayout lay{};
     // launch shapes the table was built with
     std::vector<std::pair<int, int>> shape;
-    std::vector<hmc::BatchLaunch> launches;
+    // chunks: consecutive table entries [first, first + count) and the
+    // colour-pass launches (one per kernel variant) that cover them
+    struct Chunk {
+        uint32_t first = 0, count = 0;
+        std::vector<hmc::BatchLaunch> launches;
+    };
+    std::vector<Chunk> chunks;
+    size_t chunk_bytes = 0;
     // pinned staging of the uploads, reused once the previous copy is done
     char* staging = nullptr;
     hipEvent_t upload_done = nullptr;
@@ -79,7 +96,7 @@ struct hmc_batch {
     // graph replay
     int32_t graph_sweeps = 0;
     hipStream_t cap = nullptr;
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    std::vector<std::array<hipGraphExec_t, 2>> exec;   // per chunk, per sample flag
     hmc::Timer timer;
     char err[256] = {0};
 };
@@ -97,13 +114,18 @@ int bfail(hmc_batch* B, int status, const char* what, hipError_t e = hipSuccess)
 
 void drop_graphs(hmc_batch* B)
 {
+    bool any = false;
+    for (auto& pair : B->exec)
+        for (auto g : pair) any = any || g != nullptr;
     // a replay may still be running on the stream
-    if (B->exec[0] || B->exec[1]) (void)hipStreamSynchronize(B->stream);
-    for (auto& g : B->exec)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
+    if (any) (void)hipStreamSynchronize(B->stream);
+    for (auto& pair : B->exec)
+        for (auto& g : pair)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    B->exec.assign(B->chunks.size(), {nullptr, nullptr});
 }
 
 // Waits until the staging buffer is free again (the previous upload ran).
@@ -129,41 +151,70 @@ int refresh_table(hmc_batch* B)
     if (e != hipSuccess) return bfail(B, HMC_EHIP, "waiting for the staging buffer", e);
     char* tab = B->staging + B->lay.off_tab;
     uint32_t* idx = reinterpret_cast<uint32_t*>(B->staging + B->lay.off_idx);
-    std::vector<std::vector<uint32_t>> members(hmc::kBatchGroups);
     for (size_t i = 0; i < n; ++i) {
         hmc_lattice* L = B->lat[i];
         B->shape[i] = {L->spt, L->zc};
         hmc::batch_fill_entry(tab + i * B->lay.entry, L->d, L->spt, L->zc);
-        members[hmc::batch_group(L->d, L->spt)].push_back((uint32_t)i);
     }
-    B->launches.clear();
-    const char* dev_idx = B->ws + B->lay.off_idx;
-    for (int g = 0; g < hmc::kBatchGroups; ++g) {
-        const auto& m = members[g];
-        if (m.empty()) continue;
-        uint32_t* start = idx + (size_t)g * (2 * n + 1);
-        uint32_t* ent = start + n + 1;
-        hmc::BatchLaunch bl{};
-        bl.group = g;
-        bl.tab = B->ws + B->lay.off_tab;
-        bl.start = reinterpret_cast<const uint32_t*>(dev_idx) + (size_t)g * (2 * n + 1);
-        bl.ent = bl.start + n + 1;
-        bl.n = (uint32_t)m.size();
-        uint64_t acc = 0;
-        size_t lds = 0;
-        for (size_t j = 0; j < m.size(); ++j) {
-            const hmc_lattice* L = B->lat[m[j]];
-            start[j] = (uint32_t)acc;
-            ent[j] = m[j];
-            acc += (uint64_t)hmc::pass_blocks(L->d, L->spt, L->zc);
-            lds = std::max(lds, hmc::pass_lds_bytes(B->precision, L->d.hx, L->spt));
+    // chunks of consecutive lattices: k = ceil(total / chunk_bytes) chunks
+    // of about equal bytes of spins (lattice i goes to the chunk that holds
+    // the middle of its bytes), so no chunk is left with a small remainder
+    B->chunks.clear();
+    const size_t rs = (size_t)B->precision / 8;
+    double total = 0.0;
+    for (size_t i = 0; i < n; ++i) total += (double)B->lat[i]->d.N * 3.0 * (double)rs;
+    const size_t k = B->chunk_bytes > 0 ? std::max<size_t>(1, (size_t)std::ceil(total / (double)B->chunk_bytes)) : 1;
+    const double target = total / (double)k;
+    double before = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        const double b = (double)B->lat[i]->d.N * 3.0 * (double)rs;
+        const size_t c = std::min(k - 1, (size_t)((before + 0.5 * b) / target));
+        if (B->chunks.empty() || c != B->chunks.size() - 1) {
+            hmc_batch::Chunk ch;
+            ch.first = (uint32_t)i;
+            B->chunks.push_back(std::move(ch));
         }
-        if (acc > 0x7FFFFFFFull) return bfail(B, HMC_EINVAL, "batch needs more than 2^31 work-groups per launch");
-        start[m.size()] = (uint32_t)acc;
-        bl.nblk = (uint32_t)acc;
-        bl.lds = lds;
-        bl.scale = B->ws + B->lay.off_scale;
-        B->launches.push_back(bl);
+        B->chunks.back().count += 1;
+        before += b;
+    }
+    // one launch per kernel variant present in a chunk; the work-group
+    // offsets and table indices of all launches are packed in the index
+    // region (2 m + 1 words for a launch over m lattices, 3 n words at most)
+    const uint32_t* dev_idx = reinterpret_cast<const uint32_t*>(B->ws + B->lay.off_idx);
+    size_t cursor = 0;
+    for (auto& c : B->chunks) {
+        std::vector<std::vector<uint32_t>> members(hmc::kBatchGroups);
+        for (uint32_t i = c.first; i < c.first + c.count; ++i)
+            members[hmc::batch_group(B->lat[i]->d, B->lat[i]->spt)].push_back(i);
+        for (int g = 0; g < hmc::kBatchGroups; ++g) {
+            const auto& m = members[g];
+            if (m.empty()) continue;
+            uint32_t* start = idx + cursor;
+            uint32_t* ent = start + m.size() + 1;
+            hmc::BatchLaunch bl{};
+            bl.group = g;
+            bl.tab = B->ws + B->lay.off_tab;
+            bl.start = dev_idx + cursor;
+            bl.ent = bl.start + m.size() + 1;
+            bl.n = (uint32_t)m.size();
+            cursor += 2 * m.size() + 1;
+            uint64_t acc = 0;
+            size_t lds = 0;
+            for (size_t j = 0; j < m.size(); ++j) {
+                const hmc_lattice* L = B->lat[m[j]];
+                start[j] = (uint32_t)acc;
+                ent[j] = m[j];
+                acc += (uint64_t)hmc::pass_blocks(L->d, L->spt, L->zc);
+                lds = std::max(lds, hmc::pass_lds_bytes(B->precision, L->d.hx, L->spt));
+            }
+            if (acc > 0x7FFFFFFFull)
+                return bfail(B, HMC_EINVAL, "batch needs more than 2^31 work-groups per launch");
+            start[m.size()] = (uint32_t)acc;
+            bl.nblk = (uint32_t)acc;
+            bl.lds = lds;
+            bl.scale = B->ws + B->lay.off_scale;
+            c.launches.push_back(bl);
+        }
     }
     e = upload(B, 0, B->lay.off_T);
     if (e != hipSuccess) return bfail(B, HMC_EHIP, "uploading the batch table", e);
@@ -206,35 +257,44 @@ int set_call(hmc_batch* B, const double* T, const int32_t* sample, int one_flag)
     return HMC_OK;
 }
 
-// Enqueues one sweep of every lattice on stream s.
+// Enqueues one sweep of the lattices of chunk c on stream s.
 template <class Pre, class Post>
-hipError_t enqueue_sweep(hmc_batch* B, bool obs, hipStream_t s, Pre pre, Post post)
+hipError_t enqueue_sweep(hmc_batch* B, size_t c, bool obs, hipStream_t s, Pre pre, Post post)
 {
+    const auto& ch = B->chunks[c];
     hipError_t e = hipSuccess;
     for (int colour = 0; colour < 2 && e == hipSuccess; ++colour)
-        for (const auto& bl : B->launches) {
+        for (const auto& bl : ch.launches) {
             if ((e = pre()) != hipSuccess) return e;
             if ((e = hmc::launch_pass_batch(B->precision, bl, colour, obs, s)) != hipSuccess) return e;
             if ((e = post(0)) != hipSuccess) return e;
         }
     if ((e = pre()) != hipSuccess) return e;
-    e = hmc::launch_finalize_batch(B->precision, B->ws + B->lay.off_tab, (uint32_t)B->lat.size(),
-                                   reinterpret_cast<const double*>(B->ws + B->lay.off_T),
-                                   reinterpret_cast<const int32_t*>(B->ws + B->lay.off_fin), s);
+    e = hmc::launch_finalize_batch(B->precision, B->ws + B->lay.off_tab + (size_t)ch.first * B->lay.entry, ch.count,
+                                   reinterpret_cast<const double*>(B->ws + B->lay.off_T) + ch.first,
+                                   reinterpret_cast<const int32_t*>(B->ws + B->lay.off_fin) + ch.first, s);
     if (e != hipSuccess) return e;
     return post(2);
 }
 
-hipError_t eager_sweep(hmc_batch* B, bool obs)
+hipError_t eager_sweep(hmc_batch* B, size_t c, bool obs)
 {
     if (!B->timer.on)
-        return enqueue_sweep(B, obs, B->stream, [] { return hipSuccess; }, [](int) { return hipSuccess; });
+        return enqueue_sweep(B, c, obs, B->stream, [] { return hipSuccess; }, [](int) { return hipSuccess; });
     return enqueue_sweep(
-        B, obs, B->stream, [B] { return B->timer.begin(B->stream); },
+        B, c, obs, B->stream, [B] { return B->timer.begin(B->stream); },
         [B](int k) { return B->timer.end(B->stream, k); });
 }
 
-hipError_t build_graph(hmc_batch* B, bool obs)
+// One sweep of every lattice (chunk after chunk).
+hipError_t eager_sweep_all(hmc_batch* B, bool obs)
+{
+    hipError_t e = hipSuccess;
+    for (size_t c = 0; c < B->chunks.size() && e == hipSuccess; ++c) e = eager_sweep(B, c, obs);
+    return e;
+}
+
+hipError_t build_graph(hmc_batch* B, size_t c, bool obs)
 {
     if (!B->cap) {
         hipError_t e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
@@ -245,10 +305,10 @@ hipError_t build_graph(hmc_batch* B, bool obs)
     if (e != hipSuccess) return e;
     hipError_t ee = hipSuccess;
     for (int32_t i = 0; i < B->graph_sweeps && ee == hipSuccess; ++i)
-        ee = enqueue_sweep(B, obs, B->cap, [] { return hipSuccess; }, [](int) { return hipSuccess; });
+        ee = enqueue_sweep(B, c, obs, B->cap, [] { return hipSuccess; }, [](int) { return hipSuccess; });
     e = hipStreamEndCapture(B->cap, &g);
     if (ee != hipSuccess) e = ee;
-    if (e == hipSuccess) e = hipGraphInstantiate(&B->exec[obs ? 1 : 0], g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&B->exec[c][obs ? 1 : 0], g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     return e;
 }
@@ -355,22 +415,26 @@ int batch_sweep(hmc_batch* B, const double* T, const int32_t* sample, int one_fl
     // the black pass computes the fused sums if any lattice samples; the
     // finalize flags decide per lattice whether they are used
     const bool obs = B->any_sample;
-    int32_t done = 0;
-    if (B->graph_sweeps > 0 && !B->timer.on) {
-        hipGraphExec_t& g = B->exec[obs ? 1 : 0];
-        while (n_sweeps - done >= B->graph_sweeps) {
-            if (!g) {
-                hipError_t e = build_graph(B, obs);
-                if (e != hipSuccess) return bfail(B, HMC_EHIP, "capturing the sweep graph", e);
+    // all the sweeps of one chunk before the next: the chunk stays in the
+    // Infinity Cache; each lattice still runs red, black, finalize per sweep
+    for (size_t c = 0; c < B->chunks.size(); ++c) {
+        int32_t done = 0;
+        if (B->graph_sweeps > 0 && !B->timer.on) {
+            hipGraphExec_t& g = B->exec[c][obs ? 1 : 0];
+            while (n_sweeps - done >= B->graph_sweeps) {
+                if (!g) {
+                    hipError_t e = build_graph(B, c, obs);
+                    if (e != hipSuccess) return bfail(B, HMC_EHIP, "capturing the sweep graph", e);
+                }
+                hipError_t e = hipGraphLaunch(g, B->stream);
+                if (e != hipSuccess) return bfail(B, HMC_EHIP, "replaying the sweep graph", e);
+                done += B->graph_sweeps;
             }
-            hipError_t e = hipGraphLaunch(g, B->stream);
-            if (e != hipSuccess) return bfail(B, HMC_EHIP, "replaying the sweep graph", e);
-            done += B->graph_sweeps;
         }
-    }
-    for (; done < n_sweeps; ++done) {
-        hipError_t e = eager_sweep(B, obs);
-        if (e != hipSuccess) return bfail(B, HMC_EHIP, "batch sweep launch", e);
+        for (; done < n_sweeps; ++done) {
+            hipError_t e = eager_sweep(B, c, obs);
+            if (e != hipSuccess) return bfail(B, HMC_EHIP, "batch sweep launch", e);
+        }
     }
     if (n_sweeps > 0)
         for (size_t i = 0; i < B->lat.size(); ++i) B->lat[i]->m_valid = (B->fin_last[i] & hmc::kFinSample) != 0;
@@ -426,24 +490,50 @@ int hmc_batch_tune(hmc_batch* B, const double* T, int32_t trial_sweeps)
     if (e == hipSuccess) e = hipEventCreate(&e1);
     const bool was_timing = B->timer.on;
     B->timer.on = false;
-    auto time_batch = [&](float* ms) -> int {
+    // everything is timed in the order of a sweep call: chunk after chunk,
+    // kChunkTrialSweeps sweeps each (one chunk when chunking is off)
+    auto time_chunked = [&](float* ms) -> int {
         int s2 = refresh_table(B);
         if (s2 != HMC_OK) return s2;
-        hipError_t r = eager_sweep(B, false);
+        hipError_t r = eager_sweep_all(B, false);
         if (r == hipSuccess) r = hipEventRecord(e0, B->stream);
-        for (int32_t k = 0; k < trial_sweeps && r == hipSuccess; ++k) r = eager_sweep(B, false);
+        for (size_t c = 0; c < B->chunks.size() && r == hipSuccess; ++c)
+            for (int32_t k = 0; k < std::max(trial_sweeps, kChunkTrialSweeps) && r == hipSuccess; ++k)
+                r = eager_sweep(B, c, false);
         if (r == hipSuccess) r = hipEventRecord(e1, B->stream);
         if (r == hipSuccess) r = hipEventSynchronize(e1);
         if (r == hipSuccess) r = hipEventElapsedTime(ms, e0, e1);
-        return r == hipSuccess ? HMC_OK : bfail(B, HMC_EHIP, "timing a launch shape", r);
+        return r == hipSuccess ? HMC_OK : bfail(B, HMC_EHIP, "timing a batch configuration", r);
     };
     st = e == hipSuccess ? HMC_OK : bfail(B, HMC_EHIP, "hipEventCreate", e);
+    // the chunk size with the current shapes
+    auto tune_chunk = [&]() {
+        size_t best_chunk = B->chunk_bytes;
+        float best_ms = 0.f;
+        bool first = true;
+        for (size_t cb : kChunkCandidates) {
+            if (st != HMC_OK) break;
+            B->chunk_bytes = cb;
+            B->table_valid = false;
+            float ms = 0.f;
+            st = time_chunked(&ms);
+            if (st == HMC_OK && (first || ms < best_ms)) {
+                best_ms = ms;
+                best_chunk = cb;
+                first = false;
+            }
+        }
+        B->chunk_bytes = best_chunk;
+        B->table_valid = false;
+    };
+    tune_chunk();
+    // the launch shape of each size class under that chunking
     for (const auto& members : order) {
         if (st != HMC_OK) break;
         const hmc_lattice* L0 = B->lat[members[0]];
         std::pair<int, int> best = {L0->spt, L0->zc};
         float best_ms = 0.f;
-        st = time_batch(&best_ms);
+        st = time_chunked(&best_ms);
         for (int spt : {1, 2, 4}) {
             if (hmc::pass_lds_bytes(B->precision, L0->d.hx, spt) > hmc::kMaxLds) continue;
             for (int zc = 2; zc <= 64 && zc <= L0->d.nz && st == HMC_OK; zc *= 2) {
@@ -453,7 +543,7 @@ int hmc_batch_tune(hmc_batch* B, const double* T, int32_t trial_sweeps)
                     B->lat[i]->zc = zc;
                 }
                 float ms = 0.f;
-                st = time_batch(&ms);
+                st = time_chunked(&ms);
                 if (st == HMC_OK && ms < best_ms) {
                     best_ms = ms;
                     best = {spt, zc};
@@ -465,6 +555,8 @@ int hmc_batch_tune(hmc_batch* B, const double* T, int32_t trial_sweeps)
             B->lat[i]->zc = best.second;
         }
     }
+    // and the chunk size again with the final shapes
+    tune_chunk();
     B->timer.on = was_timing;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -538,6 +630,27 @@ int hmc_batch_reset_stats(hmc_batch* B)
     if (!B) return HMC_EINVAL;
     hipError_t e = hmc::launch_reset_batch(B->precision, B->ws + B->lay.off_tab, (uint32_t)B->lat.size(), B->stream);
     if (e != hipSuccess) return bfail(B, HMC_EHIP, "clearing the accumulators", e);
+    return HMC_OK;
+}
+
+int hmc_batch_set_chunk_bytes(hmc_batch* B, int64_t bytes)
+{
+    if (!B) return HMC_EINVAL;
+    if (bytes < 0) return bfail(B, HMC_EINVAL, "chunk bytes must be >= 0");
+    if ((size_t)bytes != B->chunk_bytes) {
+        hipError_t e = staging_wait(B);
+        if (e != hipSuccess) return bfail(B, HMC_EHIP, "waiting for the staging buffer", e);
+        B->chunk_bytes = (size_t)bytes;
+        B->table_valid = false;
+        return refresh_table(B);
+    }
+    return HMC_OK;
+}
+
+int hmc_batch_get_chunk_bytes(const hmc_batch* B, int64_t* bytes)
+{
+    if (!B || !bytes) return HMC_EINVAL;
+    *bytes = (int64_t)B->chunk_bytes;
     return HMC_OK;
 }
 

@@ -137,6 +137,7 @@ def batched_mt(jobs, precision=32, equil=1000, samples=4000, block=200, seed=4, 
         t0 = time.perf_counter()
         info["shapes"] = B.tune(T, trial_sweeps)
         info["tune_s"] = time.perf_counter() - t0
+        info["chunk_bytes"] = B.chunk_bytes()
     if graph:
         B.set_graph(graph)
     torch.cuda.synchronize()

@@ -131,5 +131,7 @@ def test_batch_host_checks(hmc):
     assert L.hmc_batch_reset_stats(None) == -1
     assert L.hmc_batch_sweep_each(None, T, None, 1) == -1
     assert L.hmc_batch_set_lattices(None, None, 1) == -1
+    assert L.hmc_batch_set_chunk_bytes(None, 0) == -1
+    assert L.hmc_batch_get_chunk_bytes(None, None) == -1
     L.hmc_batch_destroy(None)
     assert L.hmc_batch_last_error(None) == b"no batch"

@@ -227,6 +227,26 @@ def test_set_lattices_reuses_the_batch(H):
     B.close()
 
 
+@pytest.mark.parametrize("chunk", [0, 1, 20000])
+def test_chunking_does_not_change_results(H, chunk):
+    """Chunk sizes from one lattice per chunk to a few: every lattice ends
+    bit for bit where it ends alone; graph replays per chunk as well."""
+    T = _temps(len(MIX), seed=13)
+    alone = _make(H, 32, seed0=240)
+    inb = _make(H, 32, seed0=240)
+    B = H.Batch(inb)
+    B.set_chunk_bytes(chunk)
+    B.sweep(T, 5)
+    B.set_graph(2)
+    B.sweep(T, 5, sample=True)
+    for g, t in zip(alone, T):
+        g.sweep(t, 5)
+        g.sweep(t, 5, sample=True)
+    for i, (a, b) in enumerate(zip(alone, inb)):
+        assert a.get_state() == b.get_state(), (chunk, MIX[i])
+    B.close()
+
+
 def test_wall_initial_state(H):
     """init = "wall" writes the T = 0 profile on the device."""
     from paper_2103_03517_amd import walls as W
