@@ -294,9 +294,10 @@ def main():
         for l in lats:
             l.set_launch(2, 16)
         B = H.Batch(lats)
+        B.set_chunk_bytes(192 << 20)      # what the autotuner chooses for this batch
         B.sweep([t for _, t in jobs], 20, sample=True)
         torch.cuda.synchronize()
-        log("profile-batch: 20 sampled sweeps of the 64-job FP32 batch")
+        log("profile-batch: 20 sampled sweeps of the 64-job FP32 batch in 192 MiB chunks")
         return
     dev = torch.cuda.get_device_properties(0)
     log(f"device: {dev.name}, {dev.multi_processor_count} CUs")
