@@ -217,6 +217,16 @@ int hmc_set_state(hmc_lattice* L, const void* host_buf, size_t bytes);
 int hmc_set_launch(hmc_lattice* L, int32_t sites_per_thread, int32_t z_chunk);
 int hmc_get_launch(const hmc_lattice* L, int32_t* sites_per_thread, int32_t* z_chunk);
 
+/* Look-ahead of the standard pass's march over z: depth 1 issues the loads
+ * of the planes one step ahead of their use, depth 2 two steps ahead (more
+ * loads in flight, for lattices that stream from HBM); 0 (the default)
+ * takes 2 when the spins exceed 256 MiB (the last-level cache) and 1
+ * otherwise.  Lattices with bond masks always use depth 1.  The spins do
+ * not depend on the depth.  hmc_get_prefetch gives the depth in use.
+ * Errors: HMC_EINVAL (depth outside 0..2, or 2 with bond masks). */
+int hmc_set_prefetch(hmc_lattice* L, int32_t depth);
+int hmc_get_prefetch(const hmc_lattice* L, int32_t* depth);
+
 /* Per-kernel timing (see hmc_timing).  Enabling resets the totals;
  * hmc_read_timing synchronises and returns the totals so far. */
 int hmc_set_timing(hmc_lattice* L, int32_t enable);

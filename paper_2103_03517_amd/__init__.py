@@ -59,7 +59,7 @@ TIMING_KINDS = ("pass", "constrained", "reduce", "other")
 SYMBOLS = ("hmc_workspace_bytes", "hmc_init_lattice", "hmc_sweep", "hmc_constrained_sweep",
            "hmc_observables", "hmc_reset_stats", "hmc_set_bond_masks", "hmc_plane_means", "hmc_copy_spins",
            "hmc_state_bytes",
-           "hmc_get_state", "hmc_set_state", "hmc_set_launch", "hmc_get_launch",
+           "hmc_get_state", "hmc_set_state", "hmc_set_launch", "hmc_get_launch", "hmc_set_prefetch", "hmc_get_prefetch",
            "hmc_set_timing", "hmc_read_timing", "hmc_destroy", "hmc_strerror",
            "hmc_last_error", "hmc_batch_workspace_bytes", "hmc_batch_create", "hmc_batch_sweep",
            "hmc_batch_tune", "hmc_batch_set_graph", "hmc_batch_set_timing",
@@ -108,6 +108,10 @@ def lib():
     L.hmc_set_launch.argtypes = [vp, i32, i32]
     L.hmc_get_launch.restype = i32
     L.hmc_get_launch.argtypes = [vp, P(i32), P(i32)]
+    L.hmc_set_prefetch.restype = i32
+    L.hmc_set_prefetch.argtypes = [vp, i32]
+    L.hmc_get_prefetch.restype = i32
+    L.hmc_get_prefetch.argtypes = [vp, P(i32)]
     L.hmc_set_timing.restype = i32
     L.hmc_set_timing.argtypes = [vp, i32]
     L.hmc_read_timing.restype = i32
@@ -292,6 +296,15 @@ class Lattice:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         self._check(self._lib.hmc_get_launch(self._h, ctypes.byref(a), ctypes.byref(b)))
         return int(a.value), int(b.value)
+
+    def set_prefetch(self, depth):
+        """Look-ahead of the pass's march: 1 or 2 planes, 0 automatic."""
+        self._check(self._lib.hmc_set_prefetch(self._h, int(depth)))
+
+    def get_prefetch(self):
+        d = ctypes.c_int32()
+        self._check(self._lib.hmc_get_prefetch(self._h, ctypes.byref(d)))
+        return int(d.value)
 
     def set_timing(self, enable=True):
         self._check(self._lib.hmc_set_timing(self._h, int(bool(enable))))

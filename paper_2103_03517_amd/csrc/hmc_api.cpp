@@ -299,6 +299,7 @@ int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes, void* h
     d.init_width = p->init_width;
     d.zbound = p->boundary_z;
     d.mask = p->bond_masks ? reinterpret_cast<uint8_t*>(base + lay.off_mask) : nullptr;
+    d.prefetch = 0;
 
     // 1 - cos(theta) = 2 sin^2(theta/2) for theta = 0..180 degrees
     for (int th = 0; th <= 180; ++th) {
@@ -681,6 +682,22 @@ int hmc_get_launch(const hmc_lattice* L, int32_t* sites_per_thread, int32_t* z_c
     if (!L || !sites_per_thread || !z_chunk) return HMC_EINVAL;
     *sites_per_thread = L->spt;
     *z_chunk = L->zc;
+    return HMC_OK;
+}
+
+int hmc_set_prefetch(hmc_lattice* L, int32_t depth)
+{
+    if (!L) return HMC_EINVAL;
+    if (depth < 0 || depth > 2) return fail(L, HMC_EINVAL, "prefetch depth must be 0, 1 or 2");
+    if (depth == 2 && L->d.mask) return fail(L, HMC_EINVAL, "lattices with bond masks look one plane ahead");
+    L->d.prefetch = depth;
+    return HMC_OK;
+}
+
+int hmc_get_prefetch(const hmc_lattice* L, int32_t* depth)
+{
+    if (!L || !depth) return HMC_EINVAL;
+    *depth = hmc::pass_deep(L->d) ? 2 : 1;
     return HMC_OK;
 }
 

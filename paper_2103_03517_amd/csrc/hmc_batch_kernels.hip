@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kThreads) void pass_batch_kernel(const BatchEntry<R
     }
     const uint32_t e = ent[lo];
     const BatchEntry<R>& E = tab[e];
-    pass_tile<R, C, OBS, SPT, HALO, false>(E.a, E.zc, E.nqb, gb - start[lo], scale[e], smem);
+    pass_tile<R, C, OBS, SPT, HALO, false, false>(E.a, E.zc, E.nqb, gb - start[lo], scale[e], smem);
 }
 
 // ---------------------------------------------------------------------------

@@ -15,6 +15,7 @@ constexpr int kNumPart = 12;         // doubles per work-group partial
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS budget of one work-group
 constexpr int kGatherBlocks = 2048;    // most work-groups of a constrained-sweep kernel
+constexpr uint64_t kDeepMarchBytes = 256ull << 20;  // spins above which the pass looks two planes ahead
 
 // Per-work-group partial sums written by the passes and reduced in a fixed
 // order by the finalize kernel.
@@ -75,7 +76,16 @@ struct DevLattice {
     double init_width;        // wall width of init_mode 2
     int32_t zbound;           // z boundary: 0 periodic, 1 anti-periodic, 2 open
     uint8_t* mask;            // [colour][Nc] active-bond bits, or null (every bond)
+    int32_t prefetch;         // look-ahead of the standard pass: 0 automatic, 1 or 2 planes
 };
+
+// The march depth of a lattice: as set, or automatically two for spins
+// larger than the last-level cache; always one with bond masks.
+inline bool pass_deep(const DevLattice& d)
+{
+    if (d.mask || d.prefetch == 1) return false;
+    return d.prefetch == 2 || (uint64_t)d.N * 3ull * (uint64_t)(d.precision / 8) > kDeepMarchBytes;
+}
 
 // Launchers (hmc_kernels.hip).  Each returns the HIP status of the launch;
 // *blocks receives the number of work-groups that wrote results.

@@ -429,15 +429,26 @@ __device__ __forceinline__ V3<R> update_site(const Model<R>& m, const V3<R>& s, 
 //
 // A work-group owns Q = 256*SPT consecutive in-plane colour indices and
 // marches over z_chunk planes.  The other colour's plane z sits in LDS as a
-// window [base - hx, base + Q + hx) (the x and y neighbours); its z-1, z and
-// z+1 values at the owned columns stay in registers.  Each plane of each
-// colour is therefore fetched once per pass (plus a halo of 2*hx entries per
-// plane), and the loads for plane z+1/z+2 are issued before plane z is
-// computed.  The march is unrolled by four so that the four register planes
-// rotate by renaming.  OBS (black pass only) fuses the observables: the black
-// site after its update plus its red x-partner (same colour index), and the
-// exchange of the black site with its six final red neighbours, so every
-// site and every bond is counted once.
+// window [base - hx, base + Q + hx) (the x and y neighbours), so each plane
+// of each colour is fetched once per pass (plus a halo of 2*hx entries per
+// plane).  Two marches share this layout and differ in how far ahead the
+// loads run:
+//
+// * depth one (march1): step z issues the other colour's plane z+2 and the
+//   own colour's plane z+1; the other colour's z-1, z, z+1 and z+2 values at
+//   the owned columns stay in registers, rotating by renaming over a march
+//   unrolled by four.  Best while the spins stay in the 256 MB last-level
+//   cache, whose latency one plane of look-ahead covers.
+// * depth two (march2): step z issues the other colour's plane z+3 and the
+//   own colour's plane z+2, so two planes of loads are in flight while one
+//   is computed; the same-index partner comes from the window and becomes
+//   the z-1 value of the next step, and three register planes rotate over a
+//   march unrolled by three.  Best for lattices that stream from HBM.
+//
+// OBS (black pass only) fuses the observables: the black site after its
+// update plus its red x-partner (same colour index), and the exchange of the
+// black site with its six final red neighbours, so every site and every bond
+// is counted once.
 // ---------------------------------------------------------------------------
 template <typename R, int SPT, int HALO>
 struct PassCtx {
@@ -455,8 +466,12 @@ struct PassCtx {
     uint32_t zbound;
 };
 
+// Depth-one march: one step, plane z = z0 + zi; the register planes om, o0,
+// op, opp hold the other colour's z-1, z, z+1 and z+2 (in flight), sc and
+// sn the own colour's z and z+1 (in flight), hp and hpp the halo's z+1 and
+// z+2 (in flight).
 template <typename R, int C, bool OBS, int SPT, int HALO, int K, bool MASK>
-__device__ __forceinline__ void pass_step(const KArgs<R>& a, const Arrays<R>& g, const PassCtx<R, SPT, HALO>& x,
+__device__ __forceinline__ void step1(const KArgs<R>& a, const Arrays<R>& g, const PassCtx<R, SPT, HALO>& x,
                                           uint32_t zi, V3<R> (&om)[SPT], V3<R> (&o0)[SPT], V3<R> (&op)[SPT],
                                           V3<R> (&opp)[SPT], V3<R> (&sc)[SPT], V3<R> (&sn)[SPT],
                                           V3<R> (&hp)[HALO], V3<R> (&hpp)[HALO], uint32_t& nacc, Acc& acc)
@@ -529,15 +544,236 @@ __device__ __forceinline__ void pass_step(const KArgs<R>& a, const Arrays<R>& g,
     __syncthreads();
 }
 
-// One work-group of a colour pass: logical tile b (column block b % nqb,
-// z-slab b / nqb) of the lattice described by a.
 template <typename R, int C, bool OBS, int SPT, int HALO, bool MASK>
+__device__ __forceinline__ void march1(const KArgs<R>& a, const Arrays<R>& g, const PassCtx<R, SPT, HALO>& x,
+                                       uint32_t& nacc, Acc& acc)
+{
+    constexpr int O = 1 - C;
+    V3<R> rA[SPT], rB[SPT], rC[SPT], rD[SPT], s0[SPT], s1[SPT], h0[HALO], h1[HALO];
+    {
+        auto plane_off = [&](int zz) -> uint32_t {
+            const int w = zz < 0 ? zz + (int)a.nz : (zz >= (int)a.nz ? zz - (int)a.nz : zz);
+            return a.P * (uint32_t)sizeof(R) * (uint32_t)w;
+        };
+        const uint32_t fm = plane_off((int)x.z0 - 1), f0 = plane_off((int)x.z0), fp = plane_off((int)x.z0 + 1);
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            rA[j] = g.get(O, x.voff[j], fm);
+            rB[j] = g.get(O, x.voff[j], f0);
+            rC[j] = g.get(O, x.voff[j], fp);
+            s0[j] = g.get(C, x.voff[j], f0);
+        }
+#pragma unroll
+        for (int i = 0; i < HALO; ++i)
+            if (x.hact[i]) {
+                LdsPlane<R>::put(x.lds[0], x.W, x.hw[i], g.get(O, x.hvoff[i], f0));
+                h0[i] = g.get(O, x.hvoff[i], fp);
+            }
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) LdsPlane<R>::put(x.lds[0], x.W, x.w[j], rB[j]);
+        // anti-periodic or open z: the z-1 plane of z0 = 0 and the z+1 plane
+        // of z0 = nz - 1 lie across the boundary (both used only as z
+        // neighbours)
+        if (x.zbound != 0 && x.z0 == 0) {
+#pragma unroll
+            for (int j = 0; j < SPT; ++j) rA[j] = across_z(rA[j], x.zbound);
+        }
+        if (x.zbound != 0 && x.z0 + 1u == a.nz) {
+#pragma unroll
+            for (int j = 0; j < SPT; ++j) rC[j] = across_z(rC[j], x.zbound);
+        }
+    }
+    __syncthreads();
+
+    uint32_t zi = 0;
+    for (; zi + 4 <= x.zn; zi += 4) {
+        step1<R, C, OBS, SPT, HALO, 0, MASK>(a, g, x, zi + 0, rA, rB, rC, rD, s0, s1, h0, h1, nacc, acc);
+        step1<R, C, OBS, SPT, HALO, 1, MASK>(a, g, x, zi + 1, rB, rC, rD, rA, s1, s0, h1, h0, nacc, acc);
+        step1<R, C, OBS, SPT, HALO, 2, MASK>(a, g, x, zi + 2, rC, rD, rA, rB, s0, s1, h0, h1, nacc, acc);
+        step1<R, C, OBS, SPT, HALO, 3, MASK>(a, g, x, zi + 3, rD, rA, rB, rC, s1, s0, h1, h0, nacc, acc);
+    }
+    if (zi < x.zn) step1<R, C, OBS, SPT, HALO, 0, MASK>(a, g, x, zi + 0, rA, rB, rC, rD, s0, s1, h0, h1, nacc, acc);
+    if (zi + 1 < x.zn) step1<R, C, OBS, SPT, HALO, 1, MASK>(a, g, x, zi + 1, rB, rC, rD, rA, s1, s0, h1, h0, nacc, acc);
+    if (zi + 2 < x.zn) step1<R, C, OBS, SPT, HALO, 2, MASK>(a, g, x, zi + 2, rC, rD, rA, rB, s0, s1, h0, h1, nacc, acc);
+
+}
+
+// Depth-two march: one step, plane z = z0 + zi.  op: the other colour's plane
+// z+1 (landed); on: the slot that receives plane z+3.  sc, sn: the own
+// colour's plane z (landed) and the slot for plane z+2; hp, hn: the halo
+// likewise; mc, mn: the masks likewise.  om holds plane z-1 on entry and
+// plane z on exit.
+//
+// Every step issues its loads unconditionally, so that the number of
+// memory operations between a load and its use is the same on every path
+// (the compiler's wait counts are then those of the steady state); the
+// planes are clamped to the last one the tile needs, so the loads of the
+// last steps re-read planes just fetched.
+template <typename R, int C, bool OBS, int SPT, int HALO, bool MASK>
+__device__ __forceinline__ void step2(const KArgs<R>& a, const Arrays<R>& g, const PassCtx<R, SPT, HALO>& x,
+                                          uint32_t zi, V3<R> (&om)[SPT], V3<R> (&op)[SPT], V3<R> (&on)[SPT],
+                                          V3<R> (&sc)[SPT], V3<R> (&sn)[SPT], V3<R> (&hp)[HALO],
+                                          V3<R> (&hn)[HALO], uint32_t (&mc)[SPT], uint32_t (&mn)[SPT],
+                                          uint32_t& nacc, Acc& acc)
+{
+    constexpr int O = 1 - C;
+    const uint32_t z = x.z0 + zi;
+    const uint32_t B = zi & 1u;
+    const uint32_t zend = x.z0 + x.zn;      // <= nz
+    auto plane_off = [&](uint32_t zz) -> uint32_t {
+        return x.P * (uint32_t)sizeof(R) * (zz >= x.nz ? zz - x.nz : zz);
+    };
+    // loads two planes ahead: the other colour's plane z+3 (the z+1
+    // neighbour of plane z+2) and the own colour's plane z+2
+    const uint32_t z3 = min(z + 3u, zend), z2 = min(z + 2u, zend - 1u);
+    const uint32_t f3 = plane_off(z3), f2 = plane_off(z2);
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        on[j] = g.get(O, x.voff[j], f3);
+        sn[j] = g.get(C, x.voff[j], f2);
+        if (MASK) mn[j] = a.mask[C][x.voff[j] / (uint32_t)sizeof(R) + x.P * z2];
+    }
+#pragma unroll
+    for (int i = 0; i < HALO; ++i) hn[i] = g.get(O, x.hvoff[i], f3);
+    // anti-periodic or open z: plane nz is plane 0 seen across the boundary
+    // (only ever the z+1 neighbour of plane nz - 1); a uniform branch taken
+    // in the top tile only
+    if (__builtin_expect(x.zbound != 0 && z3 == x.nz, 0)) {
+        __asm__ volatile("");
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) on[j] = across_z(on[j], x.zbound);
+    }
+    // plane z+1 (landed a step ago) into the other LDS buffer; its readers
+    // of the step before have passed the barrier
+    {
+        unsigned char* Ln = B ? x.lds[0] : x.lds[1];   // a select keeps the LDS addressing
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) LdsPlane<R>::put(Ln, x.W, x.w[j], op[j]);
+#pragma unroll
+        for (int i = 0; i < HALO; ++i)
+            if (x.hact[i]) LdsPlane<R>::put(Ln, x.W, x.hw[i], hp[i]);
+    }
+    const unsigned char* L = B ? x.lds[1] : x.lds[0];
+    const uint32_t fz = plane_off(z);
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        if (!x.act[j]) continue;
+        const uint32_t p = x.par[j] ^ B;
+        const V3<R> xd = LdsPlane<R>::get(L, x.W, B ? x.wd[1][j] : x.wd[0][j]);
+        const V3<R> ym = LdsPlane<R>::get(L, x.W, x.w[j] - x.hx);
+        const V3<R> yp = LdsPlane<R>::get(L, x.W, x.w[j] + x.hx);
+        const V3<R> o0 = LdsPlane<R>::get(L, x.W, x.w[j]);
+        const V3<R> xm = p ? o0 : xd;
+        const V3<R> xp = p ? xd : o0;
+        const uint32_t k = x.voff[j] / (uint32_t)sizeof(R) + x.P * z;
+        V3<R> nb;
+        if (MASK) {
+            // bonds cut by the site's mask (intergrain bonds) weigh zero
+            const uint32_t mb = mc[j];
+            const R w0 = (mb & 1u) ? R(1) : R(0), w1 = (mb & 2u) ? R(1) : R(0);
+            const R w2 = (mb & 4u) ? R(1) : R(0), w3 = (mb & 8u) ? R(1) : R(0);
+            const R w4 = (mb & 16u) ? R(1) : R(0), w5 = (mb & 32u) ? R(1) : R(0);
+            nb = V3<R>{((((w0 * xm.x + w1 * xp.x) + w2 * ym.x) + w3 * yp.x) + w4 * om[j].x) + w5 * op[j].x,
+                       ((((w0 * xm.y + w1 * xp.y) + w2 * ym.y) + w3 * yp.y) + w4 * om[j].y) + w5 * op[j].y,
+                       ((((w0 * xm.z + w1 * xp.z) + w2 * ym.z) + w3 * yp.z) + w4 * om[j].z) + w5 * op[j].z};
+        } else {
+            nb = V3<R>{((((xm.x + xp.x) + ym.x) + yp.x) + om[j].x) + op[j].x,
+                       ((((xm.y + xp.y) + ym.y) + yp.y) + om[j].y) + op[j].y,
+                       ((((xm.z + xp.z) + ym.z) + yp.z) + om[j].z) + op[j].z};
+        }
+        const Rand4 rn = philox(x.sweep, 2u * k + p, (uint32_t)C, a.inst, a.key0, a.key1);
+        const V3<R> f = update_site<R, OBS>(a.m, sc[j], nb, o0, rn, x.c1, x.scale, nacc, acc);
+        g.put(C, x.voff[j], fz, f);
+        om[j] = o0;
+    }
+    __syncthreads();
+}
+
+template <typename R, int C, bool OBS, int SPT, int HALO, bool MASK>
+__device__ __forceinline__ void march2(const KArgs<R>& a, const Arrays<R>& g, const PassCtx<R, SPT, HALO>& x,
+                                       uint32_t& nacc, Acc& acc)
+{
+    constexpr int O = 1 - C;
+    // register planes: the other colour's z-1 (om) and three rotating slots
+    // (planes z+1, z+2, z+3 at step z), the own colour's and the halo's
+    // three rotating slots, and the masks'
+    V3<R> om[SPT], oA[SPT], oB[SPT], oC[SPT], sA[SPT], sB[SPT], sC[SPT], hA[HALO], hB[HALO], hC[HALO];
+    uint32_t mA[SPT], mB[SPT], mC[SPT];
+    {
+        auto plane_off = [&](int zz) -> uint32_t {
+            const int w = zz < 0 ? zz + (int)a.nz : (zz >= (int)a.nz ? zz - (int)a.nz : zz);
+            return a.P * (uint32_t)sizeof(R) * (uint32_t)w;
+        };
+        // planes z0-1 .. z0+2 of the other colour, z0 and z0+1 of the own
+        // colour (clamped to the tile's last needed plane, as in the steps)
+        const uint32_t zend = x.z0 + x.zn;
+        const uint32_t pB = min(x.z0 + 2u, zend), sBz = min(x.z0 + 1u, zend - 1u);
+        const uint32_t fm = plane_off((int)x.z0 - 1), f0 = plane_off((int)x.z0), f1 = plane_off((int)x.z0 + 1),
+                       f2 = plane_off((int)pB), fs1 = plane_off((int)sBz);
+        // plane z0 (written to LDS below) is loaded last: waiting for it
+        // waits for every other prologue load, so no prologue load is still
+        // in flight when the march starts and the waits inside the march are
+        // set by the march alone
+        V3<R> o0[SPT], h0[HALO];
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            om[j] = g.get(O, x.voff[j], fm);
+            oA[j] = g.get(O, x.voff[j], f1);
+            oB[j] = g.get(O, x.voff[j], f2);
+            sA[j] = g.get(C, x.voff[j], f0);
+            sB[j] = g.get(C, x.voff[j], fs1);
+            if (MASK) {
+                mA[j] = a.mask[C][x.voff[j] / (uint32_t)sizeof(R) + a.P * x.z0];
+                mB[j] = a.mask[C][x.voff[j] / (uint32_t)sizeof(R) + a.P * sBz];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < HALO; ++i) {
+            hA[i] = g.get(O, x.hvoff[i], f1);
+            hB[i] = g.get(O, x.hvoff[i], f2);
+        }
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) o0[j] = g.get(O, x.voff[j], f0);
+#pragma unroll
+        for (int i = 0; i < HALO; ++i) h0[i] = g.get(O, x.hvoff[i], f0);
+#pragma unroll
+        for (int i = 0; i < HALO; ++i)
+            if (x.hact[i]) LdsPlane<R>::put(x.lds[0], x.W, x.hw[i], h0[i]);
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) LdsPlane<R>::put(x.lds[0], x.W, x.w[j], o0[j]);
+        // anti-periodic or open z: plane -1 (the z-1 neighbour of plane 0)
+        // and plane nz (the z+1 neighbour of plane nz - 1) lie across the
+        // boundary
+        if (x.zbound != 0) {
+#pragma unroll
+            for (int j = 0; j < SPT; ++j) {
+                if (x.z0 == 0) om[j] = across_z(om[j], x.zbound);
+                if (x.z0 + 1u == a.nz) oA[j] = across_z(oA[j], x.zbound);
+                if (pB == a.nz) oB[j] = across_z(oB[j], x.zbound);
+            }
+        }
+    }
+    __syncthreads();
+
+    uint32_t zi = 0;
+    for (; zi + 3 <= x.zn; zi += 3) {
+        step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 0, om, oA, oC, sA, sC, hA, hC, mA, mC, nacc, acc);
+        step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 1, om, oB, oA, sB, sA, hB, hA, mB, mA, nacc, acc);
+        step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 2, om, oC, oB, sC, sB, hC, hB, mC, mB, nacc, acc);
+    }
+    if (zi < x.zn) step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 0, om, oA, oC, sA, sC, hA, hC, mA, mC, nacc, acc);
+    if (zi + 1 < x.zn) step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 1, om, oB, oA, sB, sA, hB, hA, mB, mA, nacc, acc);
+
+}
+
+// One work-group of a colour pass: logical tile b (column block b % nqb,
+// z-slab b / nqb) of the lattice described by a, with the march of depth
+// two when DEEP.
+template <typename R, int C, bool OBS, int SPT, int HALO, bool MASK, bool DEEP>
 __device__ __forceinline__ void pass_tile(const KArgs<R>& a, const uint32_t zc, const uint32_t nqb, const uint32_t b,
                                           const R scale, unsigned char* smem)
 {
-    constexpr int O = 1 - C;
     constexpr uint32_t Q = kThreads * SPT;
-
     const Arrays<R> g(a);
     PassCtx<R, SPT, HALO> x;
     x.hx = a.hx;
@@ -583,66 +819,30 @@ __device__ __forceinline__ void pass_tile(const KArgs<R>& a, const uint32_t zc, 
         x.hvoff[i] = ((base + x.hw[i] + a.P - a.hx) % a.P) * (uint32_t)sizeof(R);
     }
 
-    V3<R> rA[SPT], rB[SPT], rC[SPT], rD[SPT], s0[SPT], s1[SPT], h0[HALO], h1[HALO];
-    {
-        auto plane_off = [&](int zz) -> uint32_t {
-            const int w = zz < 0 ? zz + (int)a.nz : (zz >= (int)a.nz ? zz - (int)a.nz : zz);
-            return a.P * (uint32_t)sizeof(R) * (uint32_t)w;
-        };
-        const uint32_t fm = plane_off((int)x.z0 - 1), f0 = plane_off((int)x.z0), fp = plane_off((int)x.z0 + 1);
-#pragma unroll
-        for (int j = 0; j < SPT; ++j) {
-            rA[j] = g.get(O, x.voff[j], fm);
-            rB[j] = g.get(O, x.voff[j], f0);
-            rC[j] = g.get(O, x.voff[j], fp);
-            s0[j] = g.get(C, x.voff[j], f0);
-        }
-#pragma unroll
-        for (int i = 0; i < HALO; ++i)
-            if (x.hact[i]) {
-                LdsPlane<R>::put(x.lds[0], x.W, x.hw[i], g.get(O, x.hvoff[i], f0));
-                h0[i] = g.get(O, x.hvoff[i], fp);
-            }
-#pragma unroll
-        for (int j = 0; j < SPT; ++j) LdsPlane<R>::put(x.lds[0], x.W, x.w[j], rB[j]);
-        // anti-periodic or open z: the z-1 plane of z0 = 0 and the z+1 plane
-        // of z0 = nz - 1 lie across the boundary (both used only as z
-        // neighbours)
-        if (x.zbound != 0 && x.z0 == 0) {
-#pragma unroll
-            for (int j = 0; j < SPT; ++j) rA[j] = across_z(rA[j], x.zbound);
-        }
-        if (x.zbound != 0 && x.z0 + 1u == a.nz) {
-#pragma unroll
-            for (int j = 0; j < SPT; ++j) rC[j] = across_z(rC[j], x.zbound);
-        }
-    }
-    __syncthreads();
-
     uint32_t nacc = 0;
     Acc acc;
-    uint32_t zi = 0;
-    for (; zi + 4 <= x.zn; zi += 4) {
-        pass_step<R, C, OBS, SPT, HALO, 0, MASK>(a, g, x, zi + 0, rA, rB, rC, rD, s0, s1, h0, h1, nacc, acc);
-        pass_step<R, C, OBS, SPT, HALO, 1, MASK>(a, g, x, zi + 1, rB, rC, rD, rA, s1, s0, h1, h0, nacc, acc);
-        pass_step<R, C, OBS, SPT, HALO, 2, MASK>(a, g, x, zi + 2, rC, rD, rA, rB, s0, s1, h0, h1, nacc, acc);
-        pass_step<R, C, OBS, SPT, HALO, 3, MASK>(a, g, x, zi + 3, rD, rA, rB, rC, s1, s0, h1, h0, nacc, acc);
-    }
-    if (zi < x.zn) pass_step<R, C, OBS, SPT, HALO, 0, MASK>(a, g, x, zi + 0, rA, rB, rC, rD, s0, s1, h0, h1, nacc, acc);
-    if (zi + 1 < x.zn) pass_step<R, C, OBS, SPT, HALO, 1, MASK>(a, g, x, zi + 1, rB, rC, rD, rA, s1, s0, h1, h0, nacc, acc);
-    if (zi + 2 < x.zn) pass_step<R, C, OBS, SPT, HALO, 2, MASK>(a, g, x, zi + 2, rC, rD, rA, rB, s0, s1, h0, h1, nacc, acc);
-
+    if constexpr (DEEP) march2<R, C, OBS, SPT, HALO, MASK>(a, g, x, nacc, acc);
+    else march1<R, C, OBS, SPT, HALO, MASK>(a, g, x, nacc, acc);
     // LDS is free after the last barrier of the march
     block_end<R, OBS>(a, C, b, nacc, acc, reinterpret_cast<double*>(smem));
 }
 
-template <typename R, int C, bool OBS, int SPT, int HALO, bool MASK>
-__global__ __launch_bounds__(kThreads) void pass_kernel(const KArgs<R> a, const uint32_t zc, const uint32_t nqb,
-                                                        const uint32_t nblk, const R scale)
+// The depth-two FP32 variants with up to two sites per thread are held to
+// 128 registers (four waves per SIMD), which they reach without spilling.
+template <typename R, int SPT, int HALO, bool DEEP>
+constexpr int pass_waves_per_eu()
+{
+    return DEEP && sizeof(R) == 4 && (SPT == 1 || (SPT == 2 && HALO <= 2)) ? 4 : 1;
+}
+
+template <typename R, int C, bool OBS, int SPT, int HALO, bool MASK, bool DEEP>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(pass_waves_per_eu<R, SPT, HALO, DEEP>())))
+void pass_kernel(const KArgs<R> a, const uint32_t zc, const uint32_t nqb, const uint32_t nblk, const R scale)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    pass_tile<R, C, OBS, SPT, HALO, MASK>(a, zc, nqb, xcd_remap(blockIdx.x, nblk), scale, smem);
+    pass_tile<R, C, OBS, SPT, HALO, MASK, DEEP>(a, zc, nqb, xcd_remap(blockIdx.x, nblk), scale, smem);
 }
+
 
 // Launch of one colour pass of one lattice; the kernel variant follows the
 // launch shape (sites per thread), the halo width and the colour.  MASK
@@ -655,8 +855,13 @@ struct PassLaunch {
         const uint32_t nqb = cdiv((uint64_t)d.P, (uint64_t)kThreads * SPT);
         const uint32_t nzb = cdiv((uint64_t)d.nz, (uint64_t)zc);
         const uint32_t nblk = nqb * nzb;
-        pass_kernel<R, C, OBS, SPT, HALO, MASK><<<nblk, kThreads, pass_lds_bytes(d.precision, d.hx, SPT), s>>>(
-            a, (uint32_t)zc, nqb, nblk, Prim<R>::scale_for(T));
+        const size_t lds = pass_lds_bytes(d.precision, d.hx, SPT);
+        if (pass_deep(d))
+            pass_kernel<R, C, OBS, SPT, HALO, MASK, true><<<nblk, kThreads, lds, s>>>(a, (uint32_t)zc, nqb, nblk,
+                                                                                      Prim<R>::scale_for(T));
+        else
+            pass_kernel<R, C, OBS, SPT, HALO, MASK, false><<<nblk, kThreads, lds, s>>>(a, (uint32_t)zc, nqb, nblk,
+                                                                                       Prim<R>::scale_for(T));
     }
 
     template <typename R, int SPT, int HALO>

@@ -98,6 +98,8 @@ def test_null_handles(hmc):
     assert L.hmc_observables(None, None) == -1
     assert L.hmc_plane_means(None, None) == -1
     assert L.hmc_set_bond_masks(None, None) == -1
+    assert L.hmc_set_prefetch(None, 1) == -1
+    assert L.hmc_get_prefetch(None, None) == -1
     assert L.hmc_state_bytes(None) == 0
     L.hmc_destroy(None)
     assert L.hmc_last_error(None) == b"no lattice"

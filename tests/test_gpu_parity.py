@@ -67,13 +67,18 @@ SHAPES = [(2, 2, 2), (4, 4, 4), (8, 8, 8), (16, 16, 16), (6, 10, 4), (2, 6, 12),
           (34, 6, 4), (12, 2, 2), (600, 2, 2), (40, 18, 6)]
 
 
+@pytest.mark.parametrize("prefetch", [1, 2])
 @pytest.mark.parametrize("shape", SHAPES)
-def test_standard_sweep_fp64_matches_reference(H, O, shape):
-    _say("standard fp64", shape)
+def test_standard_sweep_fp64_matches_reference(H, O, shape, prefetch):
+    """Both marches over z (one or two planes of look-ahead) against the
+    reference, spin by spin, every sweep."""
+    _say("standard fp64", shape, "prefetch", prefetch)
     kw = dict(inputs.random_params(sum(shape)), seed=1234 + shape[0], instance=3, theta0_deg=25)
     n = shape[0] * shape[1] * shape[2]
     S = inputs.random_unit_spins(n, 99)
     g, o = _pair(H, O, shape, kw, spins=S)
+    g.set_prefetch(prefetch)
+    assert g.get_prefetch() == prefetch
     T = 0.7
 
     def step(s):
@@ -149,15 +154,17 @@ APSHAPES = [((4, 4, 4), 2, 16), ((6, 10, 4), 1, 3), ((8, 8, 2), 1, 1), ((4, 4, 1
             ((34, 6, 4), 2, 1), ((8, 6, 10), 1, 4)]
 
 
+@pytest.mark.parametrize("prefetch", [1, 2])
 @pytest.mark.parametrize("shape,spt,zc", APSHAPES)
-def test_antiperiodic_z_fp64_matches_reference(H, O, shape, spt, zc):
-    _say("antiperiodic fp64", shape, spt, zc)
+def test_antiperiodic_z_fp64_matches_reference(H, O, shape, spt, zc, prefetch):
+    _say("antiperiodic fp64", shape, spt, zc, "prefetch", prefetch)
     kw = dict(inputs.random_params(5 * sum(shape)), seed=99 + shape[2], instance=4, theta0_deg=35,
               boundary_z="antiperiodic")
     n = shape[0] * shape[1] * shape[2]
     S = inputs.random_unit_spins(n, 321)
     g, o = _pair(H, O, shape, kw, spins=S)
     g.set_launch(spt, zc)
+    g.set_prefetch(prefetch)
     T = 0.8
 
     def step(s):
@@ -235,6 +242,30 @@ def test_bond_mask_errors(H):
     h.set_bond_masks(np.full(64, 0x3F, dtype=np.uint8))
 
 
+def test_prefetch_depth_rule_and_errors(H):
+    """Automatic depth: one plane of look-ahead while the spins fit the
+    256 MiB last-level cache, two above; masks keep depth one."""
+    small = H.Lattice(8, 8, 8, precision=64)
+    assert small.get_prefetch() == 1
+    small.set_prefetch(2)
+    assert small.get_prefetch() == 2
+    small.set_prefetch(0)
+    assert small.get_prefetch() == 1
+    for bad in (-1, 3):
+        with pytest.raises(H.HmcError):
+            small.set_prefetch(bad)
+    big = H.Lattice(256, 256, 256, precision=64)            # 384 MiB of spins
+    assert big.get_prefetch() == 2
+    big.close()
+    fits = H.Lattice(256, 256, 256, precision=32)           # 192 MiB
+    assert fits.get_prefetch() == 1
+    fits.close()
+    m = H.Lattice(4, 4, 4, precision=32, bond_masks=True)
+    assert m.get_prefetch() == 1
+    with pytest.raises(H.HmcError):
+        m.set_prefetch(2)
+
+
 def test_plane_means(H):
     """Mean spin per z plane equals the average of the spins of that plane."""
     shape = (10, 6, 8)
@@ -292,16 +323,18 @@ def test_launch_shape_does_not_change_spins(H, precision):
     kw = dict(J=1.0, Ku=0.02, Kc=-0.03, h=(0.01, 0.0, 0.02), seed=11, init="random",
               precision=precision)
     ref = None
-    for spt, zc in [(2, 16), (1, 1), (1, 5), (4, 3), (4, 64), (2, 24), (1, 1024)]:
+    for spt, zc, pf in [(2, 16, 1), (1, 1, 1), (1, 5, 1), (4, 3, 1), (4, 64, 1), (2, 24, 1), (1, 1024, 1),
+                        (2, 16, 2), (1, 1, 2), (1, 5, 2), (4, 3, 2), (2, 2, 2), (1, 1024, 2)]:
         g = H.Lattice(*shape, **kw)
         g.set_launch(spt, zc)
+        g.set_prefetch(pf)
         g.sweep(0.9, 12)
         S = g.spins()
         ob = g.observables()
         if ref is None:
             ref = (S, ob["theta_deg"], ob["accepted_last"])
         else:
-            assert np.array_equal(S, ref[0]), (spt, zc)
+            assert np.array_equal(S, ref[0]), (spt, zc, pf)
             assert ob["theta_deg"] == ref[1] and ob["accepted_last"] == ref[2]
         g.close()
 
