@@ -50,6 +50,27 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def plain_rmw_ceiling(torch, nbytes, reps=50):
+    """GB/s of torch's in-place x += 0.5 * y on two FP32 arrays of nbytes/3
+    each: the read-read-write byte pattern of one colour pass (read both
+    colours, write one) with no stencil, no random numbers and no
+    reductions, as a practical ceiling for the pass."""
+    n = nbytes // 3 // 4
+    x = torch.zeros(n, dtype=torch.float32, device="cuda")
+    y = torch.ones(n, dtype=torch.float32, device="cuda")
+    for _ in range(10):
+        x.add_(y, alpha=0.5)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        x.add_(y, alpha=0.5)
+    b.record()
+    b.synchronize()
+    s = a.elapsed_time(b) * 1e-3 / reps
+    del x, y
+    return 3 * n * 4 / s / 1e9
+
+
 def algorithmic_pass_bytes(n, precision):
     """Bytes one colour pass must move: read both colours (N sites), write one
     colour (N/2 sites); 3 components each.  36 B per update at FP32."""
@@ -341,6 +362,12 @@ def main():
                 "kernel": "pass_kernel<float> (one colour pass, 256^3)",
                 "algorithmic_bytes_per_launch": alg,
                 "avg_launch_ms": round(pass_ms, 5)}
+
+    # what a plain elementwise kernel reaches on the same bytes
+    ceiling = plain_rmw_ceiling(torch, alg)
+    roofline["plain_rmw_GBps"] = round(ceiling, 1)
+    roofline["frac_of_plain_rmw"] = round(achieved / ceiling, 4)
+    log(f"pass: {achieved:.0f} GB/s of algorithmic bytes; a plain x += y/2 over the same bytes: {ceiling:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu:
