@@ -227,6 +227,35 @@ def test_open_z_and_bond_masks_fp64_match_reference(H, O, shape, boundary, spt, 
     assert g.observables()["theta_deg"] == o.counters()[0]
 
 
+# open films without bond masks: odd, unit and even thickness, tiles that
+# start on the top or bottom plane, under both marches
+OPENSHAPES = [((8, 6, 3), 1, 2), ((4, 4, 1), 2, 1), ((10, 6, 5), 1, 16), ((6, 4, 7), 2, 3), ((8, 8, 6), 4, 4)]
+
+
+@pytest.mark.parametrize("prefetch", [1, 2])
+@pytest.mark.parametrize("shape,spt,zc", OPENSHAPES)
+def test_open_z_fp64_matches_reference(H, O, shape, spt, zc, prefetch):
+    _say("open fp64", shape, spt, zc, "prefetch", prefetch)
+    kw = dict(inputs.random_params(11 * sum(shape)), seed=71 + shape[2], instance=2, theta0_deg=30,
+              boundary_z="open")
+    n = shape[0] * shape[1] * shape[2]
+    S = inputs.random_unit_spins(n, 5 + shape[2])
+    g, o = _pair(H, O, shape, kw, spins=S)
+    g.set_launch(spt, zc)
+    g.set_prefetch(prefetch)
+    T = 0.9
+
+    def step(s):
+        g.sweep(T, sample=(s % 2 == 0))
+        return o.sweep(T, sample=(s % 2 == 0))
+
+    _compare_every_sweep(g, o, 40, step, shape)
+    a, b = g.observables(), o.observables(T)
+    for k in ("E", "E_exch"):
+        assert abs(a[k] - b[k]) <= 1e-11 * max(1.0, abs(b[k])), k
+    assert np.allclose(a["mean_E"], b["mean_E"], rtol=1e-11, atol=1e-13)
+
+
 def test_bond_mask_errors(H):
     g = H.Lattice(4, 4, 4, precision=32)
     with pytest.raises(H.HmcError):
