@@ -391,7 +391,8 @@ hipError_t launch_pass(const DevLattice& d, int colour, bool obs, int spt, int z
 {
     *blocks = pass_blocks(d, spt, zc);
     if (d.mask) return launch_pass_masked(d, colour, obs, spt, zc, T, s);
-    return PassLaunch<false>::run(d, colour, obs, spt, zc, T, s);
+    if (pass_deep(d)) return launch_pass_deep(d, colour, obs, spt, zc, T, s);
+    return PassLaunch<false, false>::run(d, colour, obs, spt, zc, T, s);
 }
 
 template <typename R>

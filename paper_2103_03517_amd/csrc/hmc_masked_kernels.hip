@@ -9,7 +9,7 @@ namespace hmc {
 
 hipError_t launch_pass_masked(const DevLattice& d, int colour, bool obs, int spt, int zc, double T, hipStream_t s)
 {
-    return PassLaunch<true>::run(d, colour, obs, spt, zc, T, s);
+    return PassLaunch<true, false>::run(d, colour, obs, spt, zc, T, s);
 }
 
 }  // namespace hmc

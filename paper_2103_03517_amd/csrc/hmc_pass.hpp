@@ -845,9 +845,11 @@ void pass_kernel(const KArgs<R> a, const uint32_t zc, const uint32_t nqb, const 
 
 
 // Launch of one colour pass of one lattice; the kernel variant follows the
-// launch shape (sites per thread), the halo width and the colour.  MASK
-// variants are instantiated only in hmc_masked_kernels.hip.
-template <bool MASK>
+// launch shape (sites per thread), the halo width and the colour.  Each
+// translation unit instantiates one family: the plain depth-one march in
+// hmc_kernels.hip, the masked one in hmc_masked_kernels.hip, the depth-two
+// march in hmc_deep_kernels.hip (so they compile in parallel).
+template <bool MASK, bool DEEP>
 struct PassLaunch {
     template <typename R, int C, bool OBS, int SPT, int HALO>
     static void go(const KArgs<R>& a, const DevLattice& d, int zc, double T, hipStream_t s)
@@ -855,13 +857,8 @@ struct PassLaunch {
         const uint32_t nqb = cdiv((uint64_t)d.P, (uint64_t)kThreads * SPT);
         const uint32_t nzb = cdiv((uint64_t)d.nz, (uint64_t)zc);
         const uint32_t nblk = nqb * nzb;
-        const size_t lds = pass_lds_bytes(d.precision, d.hx, SPT);
-        if (pass_deep(d))
-            pass_kernel<R, C, OBS, SPT, HALO, MASK, true><<<nblk, kThreads, lds, s>>>(a, (uint32_t)zc, nqb, nblk,
-                                                                                      Prim<R>::scale_for(T));
-        else
-            pass_kernel<R, C, OBS, SPT, HALO, MASK, false><<<nblk, kThreads, lds, s>>>(a, (uint32_t)zc, nqb, nblk,
-                                                                                       Prim<R>::scale_for(T));
+        pass_kernel<R, C, OBS, SPT, HALO, MASK, DEEP><<<nblk, kThreads, pass_lds_bytes(d.precision, d.hx, SPT), s>>>(
+            a, (uint32_t)zc, nqb, nblk, Prim<R>::scale_for(T));
     }
 
     template <typename R, int SPT, int HALO>
@@ -902,5 +899,7 @@ struct PassLaunch {
 
 // The colour pass of a lattice with bond masks (hmc_masked_kernels.hip).
 hipError_t launch_pass_masked(const DevLattice& d, int colour, bool obs, int spt, int zc, double T, hipStream_t s);
+// The colour pass with the depth-two march (hmc_deep_kernels.hip).
+hipError_t launch_pass_deep(const DevLattice& d, int colour, bool obs, int spt, int zc, double T, hipStream_t s);
 
 }  // namespace hmc
