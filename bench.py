@@ -343,6 +343,11 @@ def main():
         extra["fp32_384cubed"] = time_leg(H, torch, (384, 384, 384), 32, 1.0, max(K // 3, 10),
                                           max(W // 3, 5))
         log(f"  {extra['fp32_384cubed']['value'] / 1e9:.2f} G updates/s")
+        log(f"leg 4b: 464^3 FP32 standard sweeps (99.9 M spins, the paper's lattice size)")
+        extra["fp32_464cubed"] = time_leg(H, torch, (464, 464, 464), 32, 1.0, max(K // 10, 10),
+                                          max(W // 10, 5))
+        log(f"  {extra['fp32_464cubed']['value'] / 1e9:.2f} G updates/s, "
+            f"{extra['fp32_464cubed']['ms_per_step']:.3f} ms per sweep")
 
     batched = None
     if not args.main_only and not args.no_batch:
