@@ -221,8 +221,9 @@ int hmc_get_launch(const hmc_lattice* L, int32_t* sites_per_thread, int32_t* z_c
  * of the planes one step ahead of their use, depth 2 two steps ahead (more
  * loads in flight, for lattices that stream from HBM); 0 (the default)
  * takes 2 when the spins exceed 256 MiB (the last-level cache) and 1
- * otherwise.  Lattices with bond masks always use depth 1.  The spins do
- * not depend on the depth.  hmc_get_prefetch gives the depth in use.
+ * otherwise.  Lattices with bond masks always use depth 1, and so does a
+ * batch sweep (its chunks are sized to the cache).  The spins do not
+ * depend on the depth.  hmc_get_prefetch gives the depth hmc_sweep uses.
  * Errors: HMC_EINVAL (depth outside 0..2, or 2 with bond masks). */
 int hmc_set_prefetch(hmc_lattice* L, int32_t depth);
 int hmc_get_prefetch(const hmc_lattice* L, int32_t* depth);
