@@ -190,17 +190,11 @@ __device__ __forceinline__ void neighbour_indices(uint32_t k, uint32_t hx, uint3
     zp_wraps = z == nz - 1;
 }
 
-// Neighbour sums of colour C (from the AoS copy of the other colour).  With
-// OBS (C = 1, after the red pass) it also adds the one-site terms of every
-// red site (the same-index partner of black site k) to the observables.
-template <typename R, int C, bool OBS>
+// Neighbour sums of colour C (from the AoS copy of the other colour).
+template <typename R, int C>
 __global__ __launch_bounds__(kThreads) void nbsum_kernel(const KArgs<R> a, const Vec4<R>* aos, Vec4<R>* nbs)
 {
-    __shared__ double scratch[5 * kNumPart];
     const Vec4<R>* other = aos + (size_t)(1 - C) * a.Nc;
-    Acc acc;
-    // grid-stride: at most kGatherBlocks work-groups, so that the finalize
-    // has few partial records to fold
     for (uint32_t k = blockIdx.x * kThreads + threadIdx.x; k < a.Nc; k += gridDim.x * kThreads) {
         uint32_t id[6];
         bool wm, wp;
@@ -222,13 +216,6 @@ __global__ __launch_bounds__(kThreads) void nbsum_kernel(const KArgs<R> a, const
                        ((((v[0].y + v[1].y) + v[2].y) + v[3].y) + v[4].y) + v[5].y,
                        ((((v[0].z + v[1].z) + v[2].z) + v[3].z) + v[4].z) + v[5].z};
         st4<R>(nbs, k, nb);
-        if (OBS) add_site<R, true>(acc, a.m, ld4<R>(other, k));
-    }
-    if (OBS) {
-        double vv[kNumPart] = {acc.M[0], acc.M[1], acc.M[2], acc.ex, acc.eu, acc.ec, acc.ez,
-                               acc.tq[0], acc.tq[1], acc.tq[2], 0.0, 0.0};
-        block_sum<kNumPart>(vv, scratch);
-        if (threadIdx.x < kNumPart) a.part[(size_t)blockIdx.x * kNumPart + threadIdx.x] = scratch[threadIdx.x];
     }
 }
 
@@ -238,9 +225,12 @@ __global__ __launch_bounds__(kThreads) void nbsum_kernel(const KArgs<R> a, const
 // the first spin of its pair (pi^-1(a) even) runs the pair move, so the
 // first spin is read coalesced and only the partner is a random gather.  M_L
 // is the moment along eC at the start of the sweep (one value for both
-// colours, as in the paper).  OBS (black pass) adds the two black sites and
-// their exchange with their final red neighbours; since pi is a bijection
-// every black site is covered once.  Results go to row part_base + block.
+// colours, as in the paper).  OBS adds the one-site terms (moment,
+// anisotropy, Zeeman, torque) of both final spins of every pair, and in the
+// black pass also their exchange with their final red neighbours; since pi
+// is a bijection every site is covered once, and every bond once through its
+// black end.  Results go to row part_base + block (red pass: rows 0 .., black
+// pass: rows grid ..).
 template <typename R, int C, bool OBS>
 __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R>* aos, const Vec4<R>* nbs,
                                                         const V3<R> ec, const uint32_t half, const uint32_t mask,
@@ -294,7 +284,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R
                 nacc += 2;
             }
             if (OBS) {
-                acc.ex += (double)(-m.J * dot(fi, nbi)) + (double)(-m.J * dot(fj, nbj));
+                if (C == 1) acc.ex += (double)(-m.J * dot(fi, nbi)) + (double)(-m.J * dot(fj, nbj));
                 add_site<R, true>(acc, m, fi);
                 add_site<R, true>(acc, m, fj);
             }
@@ -415,11 +405,11 @@ static void constrained_go(const DevLattice& d, int step, const double eC[3], do
         return;
     }
     if (step == kNbRed) {
-        nbsum_kernel<R, 0, false><<<grid, kThreads, 0, s>>>(a, aos, nbs);
+        nbsum_kernel<R, 0><<<full, kThreads, 0, s>>>(a, aos, nbs);
         return;
     }
     if (step == kNbBlack) {
-        nbsum_kernel<R, 1, true><<<grid, kThreads, 0, s>>>(a, aos, nbs);
+        nbsum_kernel<R, 1><<<full, kThreads, 0, s>>>(a, aos, nbs);
         return;
     }
     uint32_t bits = 2;
@@ -428,7 +418,7 @@ static void constrained_go(const DevLattice& d, int step, const double eC[3], do
     const uint32_t mask = half >= 32 ? 0xFFFFFFFFu : ((1u << half) - 1u);
     const V3<R> ec{(R)eC[0], (R)eC[1], (R)eC[2]};
     const R scale = Prim<R>::scale_for(T);
-    if (step == kPairRed) pair_kernel<R, 0, false><<<grid, kThreads, 0, s>>>(a, aos, nbs, ec, half, mask, scale, 0u);
+    if (step == kPairRed) pair_kernel<R, 0, true><<<grid, kThreads, 0, s>>>(a, aos, nbs, ec, half, mask, scale, 0u);
     else pair_kernel<R, 1, true><<<grid, kThreads, 0, s>>>(a, aos, nbs, ec, half, mask, scale, grid);
 }
 
