@@ -445,6 +445,26 @@ def test_full_size_fp64_one_sweep_matches_reference(H, O):
     assert np.max(np.abs(g.spins() - o.spins())) <= TOL
 
 
+def test_paper_size_fp32_marches_agree(H):
+    """464^3 FP32 (99.9 M spins, the lattice size of the paper's timing and of
+    the bench leg, which runs the two-plane march): two sampled sweeps give
+    the same spins and the same observables with one and two planes of
+    look-ahead."""
+    _say("464^3 fp32 both marches")
+    kw = dict(J=1.0, Ku=0.005, eu=(0, 0, 1), seed=7, init="random", precision=32)
+    out = []
+    for pf in (1, 2):
+        g = H.Lattice(464, 464, 464, **kw)
+        g.set_launch(2, 16)
+        g.set_prefetch(pf)
+        g.sweep(1.0, 2, sample=True)
+        out.append((g.spins(), g.observables()))
+        g.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for k in ("E", "E_exch", "m", "theta_deg", "accepted_last"):
+        assert out[0][1][k] == out[1][1][k], k
+
+
 def test_full_size_fp32_one_sweep_tracks_reference(H, O):
     """256^3 FP32 (the benchmark's lattice and launch shape): from the same
     start, one sweep agrees with the FP64 reference site by site except where
