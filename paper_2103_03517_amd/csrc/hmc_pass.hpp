@@ -643,8 +643,8 @@ __device__ __forceinline__ void step2(const KArgs<R>& a, const Arrays<R>& g, con
 #pragma unroll
         for (int j = 0; j < SPT; ++j) on[j] = across_z(on[j], x.zbound);
     }
-    // plane z+1 (landed a step ago) into the other LDS buffer; its readers
-    // of the step before have passed the barrier
+    // plane z+1 (issued two steps ago) into the other LDS buffer; its
+    // readers of the step before have passed the barrier
     {
         unsigned char* Ln = B ? x.lds[0] : x.lds[1];   // a select keeps the LDS addressing
 #pragma unroll
