@@ -267,6 +267,8 @@ def main():
                     help="also run the batched jobs one lattice at a time, for comparison")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run a few 256^3 FP32 sweeps and nothing else (for counter runs)")
+    ap.add_argument("--profile-deep", action="store_true",
+                    help="only 10 sampled 384^3 FP32 sweeps (the two-plane march), for rocprofv3")
     ap.add_argument("--profile-constrained", action="store_true",
                     help="run a few 128^3 FP32 constrained sweeps and nothing else")
     ap.add_argument("--profile-batch", action="store_true",
@@ -299,6 +301,14 @@ def main():
         g.sweep(1.0, 10, sample=True)
         torch.cuda.synchronize()
         log("profile-pass: 10 sampled 256^3 FP32 sweeps (20 colour passes)")
+        return
+    if args.profile_deep:
+        g = H.Lattice(384, 384, 384, precision=32, J=1.0, Ku=0.005, eu=(0, 0, 1), seed=7,
+                      init="random")
+        assert g.get_prefetch() == 2
+        g.sweep(1.0, 10, sample=True)
+        torch.cuda.synchronize()
+        log("profile-deep: 10 sampled 384^3 FP32 sweeps (20 colour passes, two planes of look-ahead)")
         return
     if args.profile_constrained:
         g = H.Lattice(128, 128, 128, precision=32, J=1.0, Kc=0.05, seed=7, init="aligned",
