@@ -376,6 +376,8 @@ def main():
                 "traffic": (round(traffic) if traffic is not None else None),
                 "kernel": "pass_kernel<float> (one colour pass, 256^3)",
                 "algorithmic_bytes_per_launch": alg,
+                "note": "the 201 MB of spins stay in the 256 MB Infinity Cache; the pass is bound by its "
+                        "serial march over z (one plane of loads in flight per step), not by HBM or VALU",
                 "avg_launch_ms": round(pass_ms, 5)}
 
     # what a plain elementwise kernel reaches on the same bytes
