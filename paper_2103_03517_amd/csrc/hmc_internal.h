@@ -14,7 +14,7 @@ constexpr int kMaxHalo = 4;          // halo slots per thread: nx <= 1024
 constexpr int kNumPart = 12;         // doubles per work-group partial
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS budget of one work-group
-constexpr int kGatherBlocks = 2048;    // most work-groups of a pair kernel (each writes a record)
+constexpr int kGatherBlocks = 512;     // most work-groups of a pair kernel (each writes a record); two per CU
 constexpr uint64_t kDeepMarchBytes = 256ull << 20;  // spins above which the pass looks two planes ahead
 
 // Per-work-group partial sums written by the passes and reduced in a fixed
