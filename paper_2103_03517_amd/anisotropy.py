@@ -134,7 +134,7 @@ def analyse(scan, m_of_T, Kc, kind="cubic"):
         out.append({"T": T, "K_torque": fit_torque_amplitude([r for r in scan if r["T"] == T], dshape),
                     "K_torque_integrated": fit_cubic_amplitude(curves_tau, shape),
                     "K_energy": fit_cubic_amplitude(curves_e, shape), "m": m_of_T.get(T),
-                    "F": {str(phi): [float(v) for v in c[1]] for c, phi in zip(curves_tau, phis)}})
+                    "F": {str(c[2]): [float(v) for v in c[1]] for c in curves_tau}})
     res = {"Kc": Kc, "rows": out}
     # over every point with 0 < m < 1, and over the low-temperature range
     # m > 0.6 where the Callen-Callen law is expected to hold

@@ -138,6 +138,37 @@ def test_cone_move_is_uniform_on_the_cap(oracle_mod):
     assert sps.kstest(z, sps.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
 
 
+def test_random_start_is_uniform_on_the_sphere(oracle_mod):
+    """The random initial state is uniform on S^2 (the paper's increasing-T
+    sweeps start from a disordered state).  Archimedes' hat-box theorem: a
+    point is uniform on the unit sphere exactly when its projection on ANY
+    fixed axis is U(-1, 1) and its azimuth about that axis is U(0, 2 pi),
+    independent of the projection.  Checked on 64 x 64 x 32 = 131072 sites
+    for the z axis and for two oblique axes, with unit length to 1e-15, zero
+    mean and the isotropic second moment <S S^T> = I/3."""
+    o = oracle_mod.OracleLattice(64, 64, 32, seed=12345, instance=3, init="random")
+    S = o.spins()
+    n = len(S)
+    assert np.max(np.abs(np.linalg.norm(S, axis=1) - 1.0)) < 1e-15
+    for axis in ((0.0, 0.0, 1.0), (1.0, 1.0, 1.0), (0.2, -0.9, 0.4)):
+        a = np.asarray(axis) / np.linalg.norm(axis)
+        b1 = np.cross(a, (1.0, 0.0, 0.0) if abs(a[0]) < 0.9 else (0.0, 1.0, 0.0))
+        b1 /= np.linalg.norm(b1)
+        b2 = np.cross(a, b1)
+        proj = S @ a
+        phi = np.arctan2(S @ b2, S @ b1) % (2 * np.pi)
+        assert sps.kstest(proj, sps.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3, axis
+        assert sps.kstest(phi, sps.uniform(loc=0, scale=2 * np.pi).cdf).pvalue > 1e-3, axis
+        # projection and azimuth independent: no rank correlation
+        assert abs(sps.spearmanr(proj, phi).statistic) < 5.0 / np.sqrt(n), axis
+    # moments of the uniform distribution: <S> = 0, <S S^T> = I/3
+    assert np.max(np.abs(S.mean(axis=0))) < 5.0 * np.sqrt(1.0 / 3.0 / n)
+    assert np.max(np.abs(S.T @ S / n - np.eye(3) / 3.0)) < 5.0 * np.sqrt(4.0 / 45.0 / n)
+    # the draw is keyed: another instance gives other spins
+    o2 = oracle_mod.OracleLattice(64, 64, 32, seed=12345, instance=4, init="random")
+    assert np.mean(np.abs(o2.spins() - S) > 1e-3) > 0.99
+
+
 # --------------------------------------------------------------------------
 # Energies (Eq. 2)
 # --------------------------------------------------------------------------
