@@ -52,7 +52,7 @@ typedef enum {
     HMC_EDIM = -2,      /* lattice dimensions not even, below 2, or too large */
     HMC_ENOMEM = -3,    /* workspace too small or misaligned */
     HMC_EHIP = -4,      /* a HIP runtime call failed */
-    HMC_ESTATE = -5,    /* state buffer of the wrong size or for another lattice */
+    HMC_ESTATE = -5,    /* state buffer of the wrong size, for another lattice, or corrupt */
     HMC_ENUMERIC = -6   /* a non-finite value appeared in the reductions */
 } hmc_status;
 
@@ -203,7 +203,10 @@ int hmc_copy_spins(hmc_lattice* L, double* host_xyz, int32_t to_host);
  * cone angle, sweep counter, accumulators and the parameters it belongs
  * to); get/set copy it to/from host memory.  Because the random numbers
  * are counter-based, a restored lattice continues bit for bit.
- * hmc_set_state returns HMC_ESTATE for an image of another lattice. */
+ * hmc_set_state returns HMC_ESTATE for an image of another lattice, and for
+ * one whose chain state is out of range (a cone angle outside [1, 180],
+ * negative counters, more torque samples than samples, an acceptance count
+ * above N); the lattice is then left as it was. */
 size_t hmc_state_bytes(const hmc_lattice* L);
 int hmc_get_state(hmc_lattice* L, void* host_buf, size_t bytes);
 int hmc_set_state(hmc_lattice* L, const void* host_buf, size_t bytes);

@@ -101,6 +101,47 @@ def fit_torque_amplitude(rows, dshape):
     return num / den
 
 
+# ---------------------------------------------------------------------------
+# Eq. 4: the reduced anisotropy from the easy-axis energy of standard
+# (unconstrained) sweeps.  K_easy is the anisotropy energy per spin of the
+# ensemble magnetised along an easy axis, measured from its T = 0 value (the
+# easy direction), and K_0,hard the T = 0 energy of the hard direction on the
+# same scale.  Uniaxial, E = -Ku (S.e)^2: K_easy = Ku (1 - <(S.e)^2>) =
+# Ku + <E_uni>/N and K_0,hard = Ku (any direction perpendicular to e), so
+# k_u = (3 <(S.e)^2> - 1)/2, the mean second Legendre polynomial.  Cubic,
+# E = Kc f(S) (f = 0 along an axis, 1/3 along a body diagonal): K_easy =
+# <E_cub>/N = Kc <f> and K_0,hard = Kc/3, so k_c = 1 - 5 <f>.  Both are 1 for
+# spins frozen along the easy axis and 0 for isotropic spins (<(S.e)^2> = 1/3,
+# <f> = 1/5).
+# ---------------------------------------------------------------------------
+def k_uniaxial(E_uni, Ku):
+    """k_u = 1 - 3 K_easy / (2 K_0,hard) from the mean uniaxial energy per
+    spin E_uni = -Ku <(S.e)^2> of a run along the easy axis."""
+    K_easy = Ku + np.asarray(E_uni, dtype=float)
+    return 1.0 - 3.0 * K_easy / (2.0 * Ku)
+
+
+def k_cubic(E_cub, Kc):
+    """k_c = 1 - 5 K_easy / (3 K_0,hard) from the mean cubic energy per spin
+    E_cub = Kc <f> of a run along an easy axis (Kc > 0)."""
+    K_easy = np.asarray(E_cub, dtype=float)
+    return 1.0 - 5.0 * K_easy / (3.0 * (Kc / 3.0))
+
+
+def fit_torque_amplitude_se(rows, dshape):
+    """fit_torque_amplitude and its standard error from each row's error
+    g_se of -<tau>.e_phi (independent runs): K = sum g d / sum d^2, so
+    se(K) = sqrt(sum (d g_se)^2) / sum d^2."""
+    num = den = var = 0.0
+    for r in rows:
+        g = -float(np.dot(np.asarray(r["torque"], dtype=float), e_phi(r["phi"])))
+        d = float(dshape(float(r["theta"]), r["phi"]))
+        num += g * d
+        den += d * d
+        var += (d * float(r.get("g_se", 0.0))) ** 2
+    return num / den, math.sqrt(var) / den
+
+
 def callen_callen_exponent(K, K0, m):
     """n of K/K0 = m^n by least squares on the logarithms, through the origin."""
     x = np.log(np.asarray(m, dtype=float))

@@ -653,7 +653,15 @@ int hmc_set_state(hmc_lattice* L, const void* host_buf, size_t bytes)
     if (memcmp(&h, &mine, sizeof(h)) != 0) return fail(L, HMC_ESTATE, "state image belongs to another lattice");
     const size_t bytes_c = (size_t)L->d.Nc * (L->d.precision / 8);
     char* base = static_cast<char*>(L->d.spins);
-    memcpy(&L->init_state, in + sizeof(h), sizeof(DevState));
+    // the kernels index the cone-angle table with theta: an image whose chain
+    // state is out of range is refused before anything reaches the device
+    DevState img;
+    memcpy(&img, in + sizeof(h), sizeof(DevState));
+    if (img.theta < 1 || img.theta > 180 || img.sweep < 0 || img.samples < 0 || img.torque_samples < 0 ||
+        img.torque_samples > img.samples || img.accepted_last < 0 || img.accepted_last > L->d.N ||
+        (img.nonfinite != 0 && img.nonfinite != 1))
+        return fail(L, HMC_ESTATE, "state image holds an out-of-range cone angle or counter");
+    L->init_state = img;
     hipError_t e = hipMemcpyAsync(L->d.st, &L->init_state, sizeof(DevState), hipMemcpyHostToDevice, L->stream);
     for (int i = 0; i < 6 && e == hipSuccess; ++i)
         e = hipMemcpyAsync(base + i * L->d.pitch, in + sizeof(h) + sizeof(DevState) + i * bytes_c, bytes_c,

@@ -63,8 +63,13 @@ def _block_stats(blocks, n, T):
     se_chi = blocking_se(chi_b)
     e = float(mean_e.mean())
     se_e = float(blocking_se(mean_e[:, None])[0])
-    return {"T": T, "m": m.tolist(), "se_m": se_m.tolist(), "E": e, "se_E": se_e,
-            "chi": chi.tolist(), "se_chi": se_chi.tolist(), "blocks": nb}
+    out = {"T": T, "m": m.tolist(), "se_m": se_m.tolist(), "E": e, "se_E": se_e,
+           "chi": chi.tolist(), "se_chi": se_chi.tolist(), "blocks": nb}
+    if all("mean_Eanis" in b for b in blocks):
+        ea = np.array([b["mean_Eanis"] for b in blocks])
+        out["Eanis"] = float(ea.mean())
+        out["se_Eanis"] = float(blocking_se(ea[:, None])[0])
+    return out
 
 
 def mt_sweep(temps, size=256, precision=32, equil=2000, samples=4000, block=200, seed=7,
@@ -101,14 +106,17 @@ def block_stats_from_reads(reads, n, T):
         m1 = ns * np.asarray(r["mean_m"])
         m2 = ns * (np.asarray(r["var_m"]) + np.asarray(r["mean_m"]) ** 2)
         e1 = ns * r["mean_E"]
+        a1 = ns * r.get("mean_Eanis", 0.0)
         if prev is not None:
             k = ns - prev[0]
             mean = (m1 - prev[1]) / k
             var = (m2 - prev[2]) / k - mean ** 2
-            blocks.append({"mean_m": mean, "var_m": np.maximum(var, 0.0), "mean_E": (e1 - prev[3]) / k})
+            blocks.append({"mean_m": mean, "var_m": np.maximum(var, 0.0), "mean_E": (e1 - prev[3]) / k,
+                           "mean_Eanis": (a1 - prev[4]) / k})
         else:
-            blocks.append({"mean_m": m1 / ns, "var_m": np.asarray(r["var_m"]), "mean_E": r["mean_E"]})
-        prev = (ns, m1, m2, e1)
+            blocks.append({"mean_m": m1 / ns, "var_m": np.asarray(r["var_m"]), "mean_E": r["mean_E"],
+                           "mean_Eanis": r.get("mean_Eanis", 0.0)})
+        prev = (ns, m1, m2, e1, a1)
     return _block_stats(blocks, n, T)
 
 
@@ -190,23 +198,39 @@ def ec_of(theta_deg, phi_deg):
 
 
 def constrained_scan(thetas, phis, temps, size=128, precision=32, sweeps=3000, equil=1000,
-                     seed=3, Kc=0.05, Ku=0.0, J=1.0, log=None):
+                     seed=3, Kc=0.05, Ku=0.0, J=1.0, block=100, log=None):
     """Anisotropy energy and torque per spin with the moment held along
-    e_C(theta, phi), each run started along e_C."""
+    e_C(theta, phi), each run started along e_C.  The sampled sweeps are read
+    every `block` sweeps, so each run also carries the blocking standard
+    error of its torque along e_phi (g_se) and of its anisotropy energy."""
     out = []
     run = 0
     for phi in phis:
+        ephi = np.array([-math.sin(math.radians(phi)), math.cos(math.radians(phi)), 0.0])
         for T in temps:
             for th in thetas:
                 ec = ec_of(th, phi)
                 g = Lattice(size, size, size, precision=precision, J=J, Kc=Kc, Ku=Ku, seed=seed,
                             instance=run, init="aligned", init_dir=ec)
                 g.constrained_sweep(T, ec, equil)
-                g.constrained_sweep(T, ec, sweeps - equil, sample=True)
-                o = g.observables()
+                gb, eb, prev = [], [], (0, np.zeros(3), 0.0)
+                left = sweeps - equil
+                while left > 0:
+                    n = min(block, left)
+                    g.constrained_sweep(T, ec, n, sample=True)
+                    left -= n
+                    o = g.observables()
+                    ns = o["torque_samples"]
+                    tsum = ns * np.asarray(o["mean_torque"])
+                    esum = ns * o["mean_Eanis"]
+                    gb.append(-float((tsum - prev[1]) @ ephi) / (ns - prev[0]))
+                    eb.append((esum - prev[2]) / (ns - prev[0]))
+                    prev = (ns, tsum, esum)
                 g.close()
                 r = {"theta": th, "phi": phi, "T": T, "E_anis": o["mean_Eanis"],
-                     "E": o["mean_E"], "torque": o["mean_torque"], "m": o["mean_m"][0]}
+                     "E": o["mean_E"], "torque": o["mean_torque"], "m": o["mean_m"][0],
+                     "g_se": float(blocking_se(np.array(gb)[:, None])[0]),
+                     "E_anis_se": float(blocking_se(np.array(eb)[:, None])[0])}
                 out.append(r)
                 run += 1
                 if log:
@@ -253,6 +277,80 @@ def anisotropy_run(size=128, precision=32, thetas=tuple(range(0, 91, 10)), phis=
         for r in res["rows"]:
             log(f"T={r['T']:.2f} m={r['m']:.5f} K_torque={r['K_torque']:.5e} K_energy={r['K_energy']:.5e}")
         log(f"n (torque) = {res.get('n_torque')}, n (energy) = {res.get('n_energy')}")
+    return res
+
+
+def eq4_run(temps, kind="cubic", K=0.05, size=128, precision=32, equil=1000, samples=2000, block=100,
+            seed=3, J=1.0):
+    """Eq. 4 route: standard sweeps of one lattice per temperature, started
+    along z (the easy axis of both forms), run as one batch; k(T) from the
+    mean anisotropy energy per spin (anisotropy.k_cubic / k_uniaxial), with
+    its blocking standard error, and <|m|> from the same chains.  Returns
+    rows {T, k, se_k, m, se_m, Eanis, se_Eanis} and the wall time."""
+    import time
+    import torch
+    from . import anisotropy as A
+    kw = dict(Kc=K, Ku=0.0) if kind == "cubic" else dict(Kc=0.0, Ku=K, eu=(0.0, 0.0, 1.0))
+    t0 = time.perf_counter()
+    lats = [Lattice(size, size, size, precision=precision, J=J, seed=seed, instance=2000 + i, init="aligned",
+                    **kw) for i in range(len(temps))]
+    B = Batch(lats)
+    B.sweep(list(temps), equil)
+    reads = [[] for _ in temps]
+    for _ in range(max(samples // block, 1)):
+        B.sweep(list(temps), block, sample=True)
+        for i, o in enumerate(B.observables()):
+            reads[i].append(o)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kfun, slope = (A.k_cubic, 5.0 / K) if kind == "cubic" else (A.k_uniaxial, 1.5 / K)
+    rows = []
+    for i, T in enumerate(temps):
+        r = block_stats_from_reads(reads[i], lats[i].n, T)
+        rows.append({"T": T, "k": float(kfun(r["Eanis"], K)), "se_k": slope * r["se_Eanis"],
+                     "m": r["m"][0], "se_m": r["se_m"][0], "Eanis": r["Eanis"], "se_Eanis": r["se_Eanis"]})
+    B.close()
+    for l in lats:
+        l.close()
+    return rows, wall
+
+
+def eq4_vs_constrained(temps=(0.2, 0.4, 0.6, 0.8, 1.0, 1.2, 1.4), size=128, precision=32, Kc=0.05,
+                       thetas=tuple(range(0, 91, 10)), phis=(0.0, 45.0), sweeps=3000, equil=1000, log=None):
+    """Cubic K(T)/K(0) two ways at the same temperatures: the torque route of
+    constrained scans (Table A2) and Eq. 4 from standard sweeps along the easy
+    axis, with their standard errors, the Callen-Callen exponents of both
+    against m(T) of the standard runs, and the wall time of each route."""
+    import time
+    import torch
+    from . import anisotropy as A
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    scan = constrained_scan(list(thetas), list(phis), list(temps), size=size, precision=precision,
+                            sweeps=sweeps, equil=equil, Kc=Kc, log=log)
+    torch.cuda.synchronize()
+    t_constrained = time.perf_counter() - t0
+    e4, t_eq4 = eq4_run(list(temps), "cubic", Kc, size=size, precision=precision, equil=equil,
+                        samples=sweeps - equil)
+    rows = []
+    for r in e4:
+        T = r["T"]
+        sel = [x for x in scan if x["T"] == T]
+        Kt, se_Kt = A.fit_torque_amplitude_se(sel, A.cubic_df)
+        kt, se_kt = Kt / Kc, se_Kt / Kc
+        se = math.hypot(se_kt, r["se_k"])
+        rows.append({"T": T, "m": r["m"], "k_torque": kt, "se_k_torque": se_kt, "k_eq4": r["k"],
+                     "se_k_eq4": r["se_k"], "diff_over_se": (r["k"] - kt) / se if se > 0 else float("nan")})
+        if log:
+            log(f"T={T:.2f} m={r['m']:.5f} K/K0 torque {kt:.5f}+-{se_kt:.1e}  Eq.4 {r['k']:.5f}+-{r['se_k']:.1e}"
+                f"  diff/se {rows[-1]['diff_over_se']:+.2f}")
+    res = {"Kc": Kc, "size": size, "rows": rows, "t_constrained_s": t_constrained, "t_eq4_s": t_eq4,
+           "constrained_runs": len(scan), "sweeps_per_run": sweeps}
+    good = [x for x in rows if 0 < x["m"] < 1 and x["m"] > 0.6]
+    if len(good) >= 2:
+        ms = [x["m"] for x in good]
+        res["n_torque_low"] = A.callen_callen_exponent([x["k_torque"] for x in good], 1.0, ms)
+        res["n_eq4_low"] = A.callen_callen_exponent([x["k_eq4"] for x in good], 1.0, ms)
     return res
 
 
@@ -420,6 +518,10 @@ def main(argv=None):
     f.add_argument("--nz", type=int, default=5)
     f.add_argument("--diameter", type=float, default=16.0)
     f.add_argument("--continuous", action="store_true")
+    e4 = sub.add_parser("eq4", help="K(T)/K(0) from Eq. 4 against the constrained torque route")
+    e4.add_argument("--size", type=int, default=128)
+    e4.add_argument("--sweeps", type=int, default=3000)
+    e4.add_argument("--equil", type=int, default=1000)
     c = sub.add_parser("constrained", help="constrained-direction scan")
     c.add_argument("--size", type=int, default=128)
     c.add_argument("--precision", type=int, default=32)
@@ -442,6 +544,8 @@ def main(argv=None):
                       grains=not args.continuous, log=log)
     elif args.cmd == "stiffness":
         res = stiffness_run(shape=(args.cross, args.cross, args.nz), log=log)
+    elif args.cmd == "eq4":
+        res = eq4_vs_constrained(size=args.size, sweeps=args.sweeps, equil=args.equil, log=log)
     elif args.cmd == "anisotropy":
         res = anisotropy_run(size=args.size, sweeps=args.sweeps, equil=args.equil, log=log)
     elif args.cmd == "batched":

@@ -308,9 +308,9 @@ def test_plane_means(H):
 
 
 def test_constrained_fp64_grid_stride_size(H, O):
-    """Above 2^20 spins the constrained kernels loop over their sites (at
-    most 2048 work-groups): 128 x 128 x 68 FP64 against the reference for
-    two sampled sweeps."""
+    """Above 2^20 spins the constrained pair kernels loop over their pairs
+    (a grid-stride loop): 128 x 128 x 68 FP64 against the reference for two
+    sampled sweeps."""
     _say("constrained grid-stride 128x128x68")
     shape = (128, 128, 68)
     eC = np.array([0.2, -0.3, 0.9])
@@ -388,6 +388,96 @@ def test_checkpoint_resume_is_bit_exact(H, precision):
     other = H.Lattice(16, 8, 14, **kw)
     with pytest.raises(H.HmcError):
         other.set_state(blob)
+
+
+@pytest.mark.parametrize("field,value", [("theta", 0), ("theta", 181), ("theta", -7), ("sweep", -1),
+                                         ("samples", -3), ("torque_samples", -1)])
+def test_corrupted_state_image_is_refused(H, field, value):
+    """A state image whose chain state is out of range (a cone angle outside
+    [1, 180] degrees, negative counters) is refused with ESTATE before
+    anything reaches the device, and the lattice keeps its chain."""
+    import struct
+    g = H.Lattice(8, 6, 4, precision=64, init="random", seed=2)
+    g.sweep(0.7, 3, sample=True)
+    blob = bytearray(g.get_state())
+    before = g.spins()
+    # the image is a 112-byte header (magic, precision, nx, ny, nz, boundary,
+    # seed, instance, mask flag, J, Ku, eu, Kc, h), then the device state:
+    # int32 theta, int32 flag, then int64 sweep, accepted_last, samples,
+    # torque_samples, ...
+    off = 112
+    assert struct.unpack_from("<i", blob, off)[0] == g.observables()["theta_deg"]
+    where = {"theta": (off, "<i"), "sweep": (off + 8, "<q"), "samples": (off + 24, "<q"),
+             "torque_samples": (off + 32, "<q")}[field]
+    struct.pack_into(where[1], blob, where[0], value)
+    with pytest.raises(H.HmcError) as e:
+        g.set_state(bytes(blob))
+    assert e.value.status == H.ESTATE
+    assert np.array_equal(g.spins(), before)
+    ob = g.observables()
+    assert ob["sweeps_done"] == 3 and 1 <= ob["theta_deg"] <= 180
+
+
+def test_cone_angle_clamps_at_180_fp64(H, O):
+    """With no interactions (J = K = h = 0) every proposal has dE = 0 and is
+    accepted, so the cone angle rises by one degree per sweep from 170 and
+    then stays at 180 (Table A1's upper guard); spins, counts and angles equal
+    the reference's every sweep."""
+    _say("theta clamp at 180")
+    kw = dict(J=0.0, Ku=0.0, Kc=0.0, seed=21, instance=1, theta0_deg=170)
+    g, o = _pair(H, O, (6, 4, 8), kw, init="random")
+    thetas = []
+
+    def step(s):
+        g.sweep(0.5, sample=(s % 2 == 0))
+        acc = o.sweep(0.5, sample=(s % 2 == 0))
+        thetas.append(o.counters()[0])
+        return acc
+
+    _compare_every_sweep(g, o, 16, step, "clamp 180")
+    assert thetas == [171, 172, 173, 174, 175, 176, 177, 178, 179, 180, 180, 180, 180, 180, 180, 180]
+    assert g.observables()["accepted_last"] == 6 * 4 * 8
+    # constrained sweeps from the whole-sphere cone: pair moves can still be
+    # rejected (no real compensating spin, or the ratio of Table A2), so the
+    # angle may move either way; it and the spins equal the reference's
+    eC = (0.0, 0.6, 0.8)
+    for _ in range(3):
+        g.constrained_sweep(0.5, eC, sample=True)
+        acc = o.constrained_sweep(0.5, eC, sample=True)
+        ob = g.observables()
+        assert ob["theta_deg"] == o.counters()[0] and ob["accepted_last"] == acc
+        assert np.max(np.abs(g.spins() - o.spins())) <= TOL
+
+
+def test_cone_angle_clamps_at_1_fp64(H, O):
+    """In the aligned ground state at T = 1e-12 a proposal is accepted only
+    if it raises the energy by less than about T (a cone step of order
+    1e-12 degrees: almost never), so the cone angle falls by one degree per
+    sweep from 6 and then stays at 1 (Table A1's lower guard), in the
+    standard and the constrained sweep; spins, counts and angles equal the
+    reference's."""
+    _say("theta clamp at 1")
+    kw = dict(J=1.0, Ku=0.01, Kc=0.02, eu=(0, 0, 1), seed=22, instance=2, theta0_deg=6)
+    g, o = _pair(H, O, (8, 6, 4), kw, init="aligned", init_dir=(0, 0, 1))
+    T = 1e-12
+    thetas = []
+
+    def step(s):
+        g.sweep(T, sample=True)
+        acc = o.sweep(T, sample=True)
+        thetas.append(o.counters()[0])
+        return acc
+
+    _compare_every_sweep(g, o, 9, step, "clamp 1")
+    assert thetas == [5, 4, 3, 2, 1, 1, 1, 1, 1]
+    for _ in range(3):
+        g.constrained_sweep(T, (0, 0, 1), sample=True)
+        acc = o.constrained_sweep(T, (0, 0, 1), sample=True)
+        ob = g.observables()
+        assert ob["theta_deg"] == o.counters()[0] == 1
+        assert ob["accepted_last"] == acc
+        assert np.max(np.abs(g.spins() - o.spins())) <= TOL
+    assert np.max(np.abs(g.spins() - np.array([0.0, 0.0, 1.0]))) <= 1e-6
 
 
 def test_argument_errors(H):
@@ -481,3 +571,38 @@ def test_full_size_fp32_one_sweep_tracks_reference(H, O):
     assert np.mean(d < 1e-4) > 0.9995, np.mean(d < 1e-4)
     assert abs(ob["accepted_last"] - acc) < 1e-4 * acc
     assert ob["theta_deg"] == o.counters()[0]
+
+
+def test_constrained_fp32_128cubed_one_sweep_tracks_reference(H, O):
+    """The constrained workload at its full size and precision (128^3 FP32,
+    J = 1, Kc = 0.05, e_C = (0.6, 0, 0.8), spins along e_C, T = 0.6, the
+    benchmark's leg): from the same spins, one constrained sweep agrees with
+    the FP64 reference pair by pair except where an FP32 rounding flips a
+    near-threshold decision (the pairing and the random numbers are the
+    same); the acceptance counts agree to 1e-4 and the cone angles exactly.
+    A second sweep starts again from the GPU's spins on both sides."""
+    _say("128^3 fp32 constrained one sweep")
+    kw = dict(J=1.0, Ku=0.0, Kc=0.05, eu=(0, 0, 1), seed=7)
+    eC = (0.6, 0.0, 0.8)
+    g = H.Lattice(128, 128, 128, precision=32, init="aligned", init_dir=eC, **kw)
+    o = O.OracleLattice(128, 128, 128, init=None, **kw)
+    o.set_spins(g.spins())
+    M = np.asarray(g.observables()["M"])
+    Mp0 = M - (M @ np.asarray(eC)) * np.asarray(eC)
+    for s in range(2):
+        g.constrained_sweep(0.6, eC, sample=True)
+        acc = o.constrained_sweep(0.6, eC, sample=True)
+        ob = g.observables()
+        d = np.max(np.abs(g.spins() - o.spins()), axis=1)
+        _say("  sweep", s, "accepted", ob["accepted_last"], acc, "fraction within 1e-4:", np.mean(d < 1e-4))
+        assert np.mean(d < 1e-4) > 0.9995, (s, np.mean(d < 1e-4))
+        assert abs(ob["accepted_last"] - acc) < 1e-4 * acc, (s, ob["accepted_last"], acc)
+        assert ob["theta_deg"] == o.counters()[0]
+        # the pair moves keep the moment perpendicular to e_C: unchanged up to
+        # FP32 rounding
+        M = np.asarray(ob["M"])
+        e = np.asarray(eC)
+        Mp = M - (M @ e) * e
+        assert np.linalg.norm(Mp - Mp0) < 1e-8 * g.n, (s, Mp, Mp0)
+        Mp0 = Mp
+        o.set_spins(g.spins())

@@ -245,3 +245,113 @@ def test_direct_torque_fit_has_no_quadrature_error():
         rows = [{"theta": t, "phi": phi, "T": 0.1, "E_anis": 0.05 * A.cubic_f(t, phi),
                  "torque": A.cubic_torque(t, phi, 0.05).tolist()} for t in range(0, 91, 10)]
         assert abs(A.analyse(rows, {}, 0.05)["rows"][0]["K_torque"] / 0.05 - 1) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Eq. 4: the reduced anisotropy from the easy-axis energy of standard sweeps
+# --------------------------------------------------------------------------
+
+def test_eq4_is_one_for_spins_frozen_along_the_easy_axis():
+    """T -> 0 limit: every spin along the easy axis gives k_u = k_c = 1
+    (energies of aligned reference lattices, not a retyped formula)."""
+    from oracle import oracle as O
+    from paper_2103_03517_amd import anisotropy as A
+    Ku, Kc = 0.03, 0.05
+    o = O.OracleLattice(6, 6, 6, J=1.0, Ku=Ku, eu=(0.0, 0.6, 0.8), seed=1, init="aligned",
+                        init_dir=(0.0, 0.6, 0.8))
+    assert abs(A.k_uniaxial(o.observables(1.0)["E_uni"] / o.n, Ku) - 1.0) < 1e-14
+    for axis in ((0, 0, 1), (1, 0, 0), (0, -1, 0)):
+        o = O.OracleLattice(6, 6, 6, J=1.0, Kc=Kc, seed=1, init="aligned", init_dir=axis)
+        assert abs(A.k_cubic(o.observables(1.0)["E_cub"] / o.n, Kc) - 1.0) < 1e-14
+    # and the hard directions give the other end of the scale: k = 1 - 3/2
+    # (uniaxial, perpendicular to e) and 1 - 5/3 (cubic, body diagonal)
+    o = O.OracleLattice(6, 6, 6, J=1.0, Ku=Ku, eu=(0.0, 0.6, 0.8), seed=1, init="aligned",
+                        init_dir=(1.0, 0.0, 0.0))
+    assert abs(A.k_uniaxial(o.observables(1.0)["E_uni"] / o.n, Ku) - (1.0 - 1.5)) < 1e-14
+    o = O.OracleLattice(6, 6, 6, J=1.0, Kc=Kc, seed=1, init="aligned", init_dir=(1, 1, 1))
+    assert abs(A.k_cubic(o.observables(1.0)["E_cub"] / o.n, Kc) - (1.0 - 5.0 / 3.0)) < 1e-14
+
+
+def test_eq4_is_zero_for_isotropic_spins():
+    """T -> infinity limit: spins uniform on the sphere (<(S.e)^2> = 1/3,
+    <f> = 1/5) give k_u = k_c = 0, within five standard errors of the
+    131072-spin sample (the spread of each per-spin value is taken from the
+    sample itself)."""
+    from oracle import oracle as O
+    from paper_2103_03517_amd import anisotropy as A
+    Ku, Kc = 0.02, 0.05
+    e = np.array([0.36, 0.48, 0.8])
+    o = O.OracleLattice(64, 64, 32, J=1.0, Ku=Ku, eu=tuple(e), Kc=Kc, seed=5, init="random")
+    ob = o.observables(1.0)
+    S = o.spins()
+    n = o.n
+    ku = A.k_uniaxial(ob["E_uni"] / n, Ku)
+    kc = A.k_cubic(ob["E_cub"] / n, Kc)
+    sd_u = np.std(1.5 * (S @ e) ** 2)
+    x2, y2, z2 = (S ** 2).T
+    sd_c = np.std(5.0 * (x2 * y2 + x2 * z2 + y2 * z2))
+    assert abs(ku) < 5 * sd_u / np.sqrt(n), (ku, sd_u)
+    assert abs(kc) < 5 * sd_c / np.sqrt(n), (kc, sd_c)
+
+
+def test_eq4_free_spins_match_boltzmann_integrals():
+    """Non-interacting spins (J = 0) at finite temperature: the chain's k_u
+    equals <P_2(cos theta)> of the Boltzmann weight exp(Ku cos^2 theta / T),
+    and its k_c equals 1 - 5 <f> of exp(-Kc f / T) over the sphere (scipy
+    quadrature), within four standard errors."""
+    from oracle import oracle as O
+    from paper_2103_03517_amd import anisotropy as A
+    from scipy import integrate
+    from tests.stats import batch_mean_se
+    T = 0.5
+    Ku = 1.0
+    w = lambda x: np.exp(Ku * x * x / T)
+    p2 = integrate.quad(lambda x: 0.5 * (3 * x * x - 1) * w(x), 0, 1)[0] / integrate.quad(w, 0, 1)[0]
+    o = O.OracleLattice(8, 8, 8, J=0.0, Ku=Ku, seed=31, init="aligned")
+    o.sweep(T, 100)
+    o.sweep(T, 2000, sample=True)
+    mean, se = batch_mean_se(A.k_uniaxial(o.samples()[:, 5], Ku))
+    assert abs(mean - p2) < 4 * se + 1e-4, (mean, p2, se)
+
+    Kc = 1.0
+
+    def f(th, ph):
+        s, c = np.sin(th), np.cos(th)
+        x2, y2, z2 = (s * np.cos(ph)) ** 2, (s * np.sin(ph)) ** 2, c * c
+        return x2 * y2 + x2 * z2 + y2 * z2
+
+    wz = integrate.dblquad(lambda th, ph: np.exp(-Kc * f(th, ph) / T) * np.sin(th), 0, 2 * np.pi, 0, np.pi)[0]
+    wf = integrate.dblquad(lambda th, ph: f(th, ph) * np.exp(-Kc * f(th, ph) / T) * np.sin(th),
+                           0, 2 * np.pi, 0, np.pi)[0]
+    kc_exact = 1.0 - 5.0 * wf / wz
+    o = O.OracleLattice(8, 8, 8, J=0.0, Kc=Kc, seed=32, init="aligned")
+    o.sweep(T, 100)
+    o.sweep(T, 2000, sample=True)
+    mean, se = batch_mean_se(A.k_cubic(o.samples()[:, 5], Kc))
+    assert abs(mean - kc_exact) < 4 * se + 1e-4, (mean, kc_exact, se)
+
+
+def test_torque_amplitude_error_propagation():
+    """fit_torque_amplitude_se: the fit equals fit_torque_amplitude, and its
+    error is the exact linear propagation of independent row errors (checked
+    against the spread of refits over resampled rows)."""
+    from paper_2103_03517_amd import anisotropy as A
+    rng = np.random.default_rng(3)
+    Kc = 0.05
+    rows = []
+    for phi in (0.0, 45.0):
+        for t in range(0, 91, 10):
+            tau = A.cubic_torque(t, phi, Kc)
+            rows.append({"theta": float(t), "phi": phi, "torque": tau.tolist(), "g_se": 1e-4})
+    K, se = A.fit_torque_amplitude_se(rows, A.cubic_df)
+    assert abs(K - A.fit_torque_amplitude(rows, A.cubic_df)) < 1e-15
+    assert abs(K / Kc - 1) < 1e-12
+    fits = []
+    for _ in range(2000):
+        rr = []
+        for r in rows:
+            g = 1e-4 * rng.normal()
+            ep = A.e_phi(r["phi"])
+            rr.append(dict(r, torque=(np.asarray(r["torque"]) - g * ep).tolist()))
+        fits.append(A.fit_torque_amplitude(rr, A.cubic_df))
+    assert abs(np.std(fits) / se - 1) < 0.08, (np.std(fits), se)
