@@ -236,6 +236,34 @@ int hmc_get_prefetch(const hmc_lattice* L, int32_t* depth);
 int hmc_set_timing(hmc_lattice* L, int32_t enable);
 int hmc_read_timing(hmc_lattice* L, hmc_timing* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * measurement that hmc_observables makes of a lattice's current spins (M,
+ * m = |M|/N, the energy terms of Eq. 2 with every bond once, the anisotropy
+ * torque), on spins held by the caller and without a lattice handle or a
+ * workspace.  The reduction scratch (per-work-group partials and the reduced
+ * values) lives in a static device array of the library: 6.5 MiB per GPU,
+ * held from the first call on that GPU until the process ends.
+ *   p:         the lattice's parameters (validated as by hmc_init_lattice;
+ *              bond_masks must be 0);
+ *   dev_spins: device memory (256-byte aligned, at least spins_bytes bytes,
+ *              owned by the caller, only read) holding the spins in the
+ *              layout of a lattice workspace: six component arrays (colour 0
+ *              x, y, z, then colour 1 x, y, z) of N/2 reals each, one every
+ *              pitch = N/2 * precision/8 bytes rounded up to a multiple of
+ *              256 -- the first 6*pitch bytes of a workspace laid out by
+ *              hmc_init_lattice for p;
+ *   out:       receives n, precision, M, m, E and its terms and torque; the
+ *              counters and averages are 0 (there is no chain).
+ * Work goes to hip_stream on the current device (which must be the stream's),
+ * and the call synchronises it.  N above 2^25 spins: HMC_EDIM.  Calls on one
+ * GPU share its scratch array: calls that overlap on one GPU (from two host
+ * threads, or on two streams) race and must be serialised by the caller.
+ * Errors: HMC_EINVAL, HMC_EDIM, HMC_ENOMEM (spins_bytes below 6*pitch, or
+ * misaligned), HMC_EHIP, HMC_ENUMERIC (out filled). */
+int hmc_measure_static(const hmc_params* p, const void* dev_spins, size_t spins_bytes, void* hip_stream,
+                       hmc_obs* out);
+
 void hmc_destroy(hmc_lattice* L);
 const char* hmc_strerror(int status);
 const char* hmc_last_error(const hmc_lattice* L);

@@ -12,7 +12,7 @@ import os
 import numpy as np
 import torch
 
-__all__ = ["Lattice", "Batch", "HmcError", "lib", "LIB_PATH", "SYMBOLS"]
+__all__ = ["Lattice", "Batch", "HmcError", "lib", "measure_static", "LIB_PATH", "SYMBOLS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhmc.so")
@@ -65,7 +65,8 @@ SYMBOLS = ("hmc_workspace_bytes", "hmc_init_lattice", "hmc_sweep", "hmc_constrai
            "hmc_batch_tune", "hmc_batch_set_graph", "hmc_batch_set_timing",
            "hmc_batch_read_timing", "hmc_batch_destroy", "hmc_batch_last_error",
            "hmc_batch_observables", "hmc_batch_reset_stats", "hmc_batch_sweep_each",
-           "hmc_batch_set_lattices", "hmc_batch_set_chunk_bytes", "hmc_batch_get_chunk_bytes")
+           "hmc_batch_set_lattices", "hmc_batch_set_chunk_bytes", "hmc_batch_get_chunk_bytes",
+           "hmc_measure_static")
 
 _lib = None
 
@@ -152,6 +153,8 @@ def lib():
     L.hmc_batch_set_chunk_bytes.argtypes = [vp, ctypes.c_int64]
     L.hmc_batch_get_chunk_bytes.restype = i32
     L.hmc_batch_get_chunk_bytes.argtypes = [vp, P(ctypes.c_int64)]
+    L.hmc_measure_static.restype = i32
+    L.hmc_measure_static.argtypes = [P(Params), vp, ctypes.c_size_t, vp, P(Obs)]
     _lib = L
     return L
 
@@ -314,6 +317,23 @@ class Lattice:
         self._check(self._lib.hmc_read_timing(self._h, ctypes.byref(t)))
         return {k: {"count": int(t.count[i]), "total_ms": float(t.total_ms[i])}
                 for i, k in enumerate(TIMING_KINDS)}
+
+
+def measure_static(params, dev_spins, nbytes, stream=None, check=True):
+    """hmc_measure_static: M, the energy terms and the torque of spins in the
+    lattice layout at device address dev_spins (nbytes long), with the
+    library's static scratch instead of a workspace.  Returns the observables
+    dict (instantaneous fields only) with its status."""
+    L = lib()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    o = Obs()
+    st = L.hmc_measure_static(ctypes.byref(params), ctypes.c_void_p(int(dev_spins)), int(nbytes),
+                              ctypes.c_void_p(s.cuda_stream), ctypes.byref(o))
+    if check and st != OK:
+        raise HmcError(st, L.hmc_strerror(st).decode())
+    d = _obs_dict(o)
+    d["status"] = st
+    return d
 
 
 def _timing_dict(t):

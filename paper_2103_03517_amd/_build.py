@@ -13,7 +13,8 @@ LIB = os.path.join(HERE, "libhmc.so")
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, "hmc_api.cpp"), os.path.join(CSRC, "hmc_batch.cpp"),
            os.path.join(CSRC, "hmc_kernels.hip"), os.path.join(CSRC, "hmc_batch_kernels.hip"),
-           os.path.join(CSRC, "hmc_masked_kernels.hip"), os.path.join(CSRC, "hmc_deep_kernels.hip")]
+           os.path.join(CSRC, "hmc_masked_kernels.hip"), os.path.join(CSRC, "hmc_deep_kernels.hip"),
+           os.path.join(CSRC, "hmc_static.hip")]
 ARCH = os.environ.get("HMC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -180,6 +180,18 @@ Layout layout_for(const hmc_params* p)
     return L;
 }
 
+}  // namespace
+
+namespace hmc {
+
+int check_params(const hmc_params* p, char* msg, size_t n) { return validate(p, msg, n); }
+
+size_t spin_pitch(const hmc_params* p) { return layout_for(p).pitch; }
+
+}  // namespace hmc
+
+namespace {
+
 struct StateHeader {
     uint32_t magic, precision;
     int32_t nx, ny, nz, boundary_z;

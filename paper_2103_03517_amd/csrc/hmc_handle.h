@@ -41,6 +41,12 @@ struct Timer {
     void destroy();
 };
 
+// Validation of a parameter block (HMC_OK or the status hmc_init_lattice
+// would return, with a message), and the byte pitch of its spin component
+// arrays in a workspace (the six arrays lie at 0, pitch, .., 5 pitch).
+int check_params(const hmc_params* p, char* msg, size_t n);
+size_t spin_pitch(const hmc_params* p);
+
 // Observables in two halves, so that a batch can read many lattices with one
 // synchronisation: enqueue the measurement and the copy of the device state
 // into host_dst (which must stay valid until the stream is synchronised),
