@@ -17,24 +17,18 @@ def voronoi_grains(nx, ny, mean_diameter, seed):
     """Grain index of every (y, x) column: nearest of n_g seeds, with
     n_g = nx ny / (pi d^2 / 4) for the mean grain diameter d (lattice
     sites).  Returns (grain map of shape (ny, nx), number of grains)."""
+    from scipy.spatial import cKDTree
     ng = max(1, int(round(nx * ny / (math.pi * mean_diameter ** 2 / 4.0))))
     rng = np.random.default_rng(seed)
     sx = rng.uniform(0, nx, ng)
     sy = rng.uniform(0, ny, ng)
-    x = np.arange(nx) + 0.5
-    y = np.arange(ny) + 0.5
-    best = np.full((ny, nx), np.inf)
-    grain = np.zeros((ny, nx), dtype=np.int64)
-    for g in range(ng):        # one pass per seed keeps the memory at one plane
-        dx = np.abs(x[None, :] - sx[g])
-        dy = np.abs(y[:, None] - sy[g])
-        dx = np.minimum(dx, nx - dx)
-        dy = np.minimum(dy, ny - dy)
-        d2 = dx ** 2 + dy ** 2
-        closer = d2 < best
-        best[closer] = d2[closer]
-        grain[closer] = g
-    return grain, ng
+    # nearest seed of every column centre on the periodic nx x ny torus (a
+    # k-d tree with periodic box: 1024^2 columns and 2 10^4 seeds in about a
+    # second)
+    tree = cKDTree(np.stack([sx, sy], axis=1), boxsize=(float(nx), float(ny)))
+    yy, xx = np.meshgrid(np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    _, idx = tree.query(np.stack([xx.ravel(), yy.ravel()], axis=1))
+    return idx.reshape(ny, nx).astype(np.int64), ng
 
 
 def grain_bond_masks(grain, nz):

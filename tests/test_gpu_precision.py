@@ -62,16 +62,19 @@ def test_block_statistics_match_the_accumulators(P):
 
 
 def test_batched_fp32_jobs_match_fp64(P):
-    """The batched FP32 jobs against the same jobs run as an FP64 batch: every
-    job within 4 combined standard errors (8 jobs x 3 observables), and
-    |dm| <= 1e-3 where the fluctuations allow it (T <= 0.6 at these sizes)."""
+    """The batched FP32 jobs against the same jobs run as an FP64 batch with
+    independent random keys (so the two standard errors add in quadrature):
+    every job's m(T) = <|m|> and <E>/N within 3 combined blocking errors, and
+    |dm| <= 1e-3 wherever the resolution allows it (3 SE < 1e-3); <m_z> and
+    chi_l are printed.  The results are deterministic (keyed random numbers),
+    so a pass is a fixed fact of this build, not a draw; with honest errors a
+    3 SE gate on 16 comparisons fails by chance for about one key in twenty."""
     jobs = [(32, 0.3), (48, 0.5), (32, 0.6), (48, 0.9), (32, 1.2), (48, 1.3), (32, 1.6), (48, 0.1)]
-    kw = dict(equil=500, samples=6000, block=300)
-    r32, _ = P.batched_mt(jobs, 32, tune=False, **kw)
-    r64, _ = P.batched_mt(jobs, 64, tune=False, **kw)
+    kw = dict(equil=1000, samples=24000, block=600)
+    r32, _ = P.batched_mt(jobs, 32, tune=False, seed=4, **kw)
+    r64, _ = P.batched_mt(jobs, 64, tune=False, seed=5, **kw)
     for c in P.compare_precisions(r32, r64):
         print(c, file=sys.stderr, flush=True)
-        assert c["dm_over_se"] <= 4.0, c
-        assert c["dE_over_se"] <= 4.0, c
-        if c["T"] <= 0.6:
-            assert c["dm"] <= 1e-3, c
+        assert c["dm_over_se"] <= 3.0, c
+        assert c["dE_over_se"] <= 3.0, c
+        assert c["pass"], c

@@ -37,13 +37,31 @@ def test_batched_workload_recipe():
 
 
 def test_compare_precisions_units():
-    a = [{"edge": 8, "T": 1.0, "m": [0.5, 0, 0, 0.5], "se_m": [3e-4, 0, 0, 4e-4], "E": -2.0, "se_E": 1e-4}]
-    b = [{"edge": 8, "T": 1.0, "m": [0.5005, 0, 0, 0.5], "se_m": [4e-4, 0, 0, 3e-4], "E": -2.0001,
-          "se_E": 1e-4}]
+    def job(m, se_m, mz, se_mz, E, se_E, chi=1.0, se_chi=0.1):
+        return {"edge": 8, "T": 1.0, "m": [m, 0, 0, mz], "se_m": [se_m, 0, 0, se_mz], "E": E, "se_E": se_E,
+                "chi": [chi, 0, 0, 0], "se_chi": [se_chi, 0, 0, 0]}
+    a = [job(0.5, 3e-4, 0.5, 4e-4, -2.0, 1e-4)]
+    b = [job(0.5005, 4e-4, 0.5, 3e-4, -2.0001, 1e-4, chi=1.2)]
     r = P.compare_precisions(a, b)[0]
     assert abs(r["dm"] - 5e-4) < 1e-12
     assert abs(r["dm_over_se"] - 1.0) < 1e-9
     assert abs(r["dE_over_se"] - 1e-4 / np.hypot(1e-4, 1e-4)) < 1e-9
+    assert abs(r["dchi_over_se"] - 0.2 / np.hypot(0.1, 0.1)) < 1e-9
+    assert r["resolves_1e-3"] is False and r["pass"] is True    # 3 SE = 1.5e-3
+    # m_z is reported, not gated
+    b = [job(0.5005, 4e-4, 0.51, 3e-4, -2.0001, 1e-4)]
+    r = P.compare_precisions(a, b)[0]
+    assert r["dmz_over_se"] > 3 and r["pass"] is True
+    # an unresolvable job (3 SE >= 1e-3) outside 1e-3 passes on the 3 SE rule
+    # alone; a resolvable one outside 1e-3 fails (it is then also beyond
+    # 3 SE: the 1e-3 rule adds nothing where it applies)
+    r = P.compare_precisions([job(0.5, 5e-4, 0.5, 0, -2.0, 1e-4)], [job(0.5011, 1e-4, 0.5, 0, -2.0, 1e-4)])[0]
+    assert r["resolves_1e-3"] is False and r["dm_over_se"] <= 3 and r["pass"] is True
+    r = P.compare_precisions([job(0.5, 2e-4, 0.5, 0, -2.0, 1e-4)], [job(0.50105, 1.5e-4, 0.5, 0, -2.0, 1e-4)])[0]
+    assert r["resolves_1e-3"] is True and r["dm_over_se"] > 3 and r["pass"] is False
+    # energies beyond 3 SE fail
+    r = P.compare_precisions([job(0.5, 2e-4, 0.5, 0, -2.0, 1e-4)], [job(0.5, 2e-4, 0.5, 0, -2.001, 1e-4)])[0]
+    assert r["dE_over_se"] > 3 and r["pass"] is False
 
 
 def test_serving_job_schedule_and_stream():
