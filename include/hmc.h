@@ -120,19 +120,23 @@ typedef struct {
 } hmc_obs;
 
 /* Per-kernel timing collected with HIP events on the handle's stream while
- * timing is enabled.  Kinds: 0 = standard colour pass, 1 = constrained sweep
- * kernels (neighbour sums and pair passes), 2 = reductions (the per-sweep finalize: cone angle, counters,
- * accumulators; and the measurement of the current spins),
- * 3 = initialisation. */
+ * timing is enabled.  Kinds: 0 = standard colour pass, 1 = constrained pair
+ * pass, 2 = reductions (the per-sweep finalize: cone angle, counters,
+ * accumulators; and the measurement of the current spins), 3 = the rest:
+ * initialisation, the copies in and out of a constrained call, and its
+ * neighbour-sum stencils (between sweeps launched together with the
+ * finalize). */
 typedef struct {
     int64_t count[4];
     double  total_ms[4];
 } hmc_timing;
 
 /* Size in bytes of the device workspace for these parameters, 0 if the
- * parameters are invalid: 36 bytes per spin at FP32 (72 at FP64) -- the
- * spins, and the working copy and neighbour sums of constrained sweeps --
- * plus a few MB of reduction partials. */
+ * parameters are invalid: 44 bytes per spin at FP32 (88 at FP64) -- the
+ * spins (12), and the working copies of constrained sweeps: the spins as
+ * 4-vectors (16) and, for the colour being paired, a record of each site's
+ * spin and neighbour sum (16 per spin) -- plus a few MB of reduction
+ * partials. */
 size_t hmc_workspace_bytes(const hmc_params* p);
 
 /* Validates p, lays the lattice out in dev_ws (device memory, 256-byte

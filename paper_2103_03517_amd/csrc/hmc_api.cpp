@@ -159,12 +159,10 @@ Layout layout_for(const hmc_params* p)
     const size_t rs = p->precision / 8;
     L.pitch = align_up(Nc * rs, hmc::kAlign);
     size_t off = 6 * L.pitch;
-    // constrained sweeps: AoS working copy of both colours and the neighbour
-    // sums of one colour, 4 reals per site
+    // constrained sweeps: an AoS copy of both colours (4 reals per site),
+    // then the records (spin, neighbour sum: 8 reals) of one colour
     L.off_aos = off;
-    off += align_up(2 * Nc * 4 * rs, hmc::kAlign);
-    L.off_nbs = off;
-    off += align_up(Nc * 4 * rs, hmc::kAlign);
+    off += align_up(2 * Nc * 4 * rs + Nc * 8 * rs, hmc::kAlign);
     L.off_state = off;
     off += align_up(sizeof(DevState), hmc::kAlign);
     L.off_c1 = off;
@@ -289,7 +287,6 @@ int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes, void* h
     d.pitch = lay.pitch;
     d.spins = base;
     d.aos = base + lay.off_aos;
-    d.nbs = base + lay.off_nbs;
     d.st = reinterpret_cast<DevState*>(base + lay.off_state);
     d.c1tab = p->precision == 64 ? static_cast<const void*>(base + lay.off_c1)
                                  : static_cast<const void*>(base + lay.off_c1 + 181 * sizeof(double));
@@ -387,14 +384,20 @@ int hmc_constrained_sweep(hmc_lattice* L, double T, const double eC[3], int32_t 
         return launch(L, kind, what, [&] { return launch_constrained(L->d, which, e, T, L->stream, &nb); });
     };
     int st = step(3, hmc::kAosIn, "copy to the AoS working copy");
+    if (st == HMC_OK) st = step(3, hmc::kNbRed, "red neighbour sums");
+    const int fin = hmc::kFinCounts | hmc::kFinObs | hmc::kFinTorque | (sample ? hmc::kFinSample : 0);
     for (int32_t it = 0; it < n_sweeps && st == HMC_OK; ++it) {
-        st = step(1, hmc::kNbRed, "red neighbour sums");
-        if (st == HMC_OK) st = step(1, hmc::kPairRed, "red pair pass");
-        if (st == HMC_OK) st = step(1, hmc::kNbBlack, "black neighbour sums");
+        st = step(1, hmc::kPairRed, "red pair pass");
+        if (st == HMC_OK) st = step(3, hmc::kNbBlack, "black neighbour sums");
         if (st == HMC_OK) st = step(1, hmc::kPairBlack, "black pair pass");
-        if (st == HMC_OK)
+        // the finalize; before another sweep, in one launch with that
+        // sweep's red neighbour sums
+        if (st == HMC_OK && it + 1 < n_sweeps)
+            st = launch(L, 3, "finalize and red neighbour sums", [&] {
+                return hmc::launch_finalize_nbsum(L->d, nb, fin, T, L->stream);
+            });
+        else if (st == HMC_OK)
             st = launch(L, 2, "finalize kernel", [&] {
-                const int fin = hmc::kFinCounts | hmc::kFinObs | hmc::kFinTorque | (sample ? hmc::kFinSample : 0);
                 return hmc::launch_finalize(L->d, nb, nb, 2 * nb, fin, T, L->stream);
             });
     }

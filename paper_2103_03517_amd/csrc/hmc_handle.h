@@ -17,7 +17,7 @@ namespace hmc {
 
 // Offsets of the regions of a lattice workspace.
 struct Layout {
-    size_t pitch, off_aos, off_nbs, off_state, off_c1, off_part, off_cnt, off_mask, total;
+    size_t pitch, off_aos, off_state, off_c1, off_part, off_cnt, off_mask, total;
     int64_t max_blocks;
 };
 

@@ -14,7 +14,6 @@ constexpr int kMaxHalo = 4;          // halo slots per thread: nx <= 1024
 constexpr int kNumPart = 12;         // doubles per work-group partial
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS budget of one work-group
-constexpr int kGatherBlocks = 512;     // most work-groups of a pair kernel (each writes a record); two per CU
 constexpr uint64_t kDeepMarchBytes = 256ull << 20;  // spins above which the pass looks two planes ahead
 
 // Per-work-group partial sums written by the passes and reduced in a fixed
@@ -64,8 +63,8 @@ struct DevLattice {
     void* spins;              // [colour][component][Nc] of float or double
     DevState* st;
     const void* c1tab;        // 181 reals: 1 - cos(theta) for theta in degrees
-    void* aos;                // constrained sweeps: [colour][Nc] 4-vectors of the spins
-    void* nbs;                // constrained sweeps: [Nc] 4-vectors of neighbour sums
+    void* aos;                // constrained sweeps: [colour][Nc] 4-vectors of the spins, then [Nc]
+                              // records (spin, neighbour sum) of the colour being paired
     double* part;             // [max_blocks][kNumPart]
     uint32_t* cnt;            // [2][max_blocks]
     int64_t max_blocks;
@@ -97,6 +96,9 @@ hipError_t launch_pass(const DevLattice& d, int colour, bool obs, int spt, int z
 enum ConstrainedStep { kAosIn = 0, kNbRed, kPairRed, kNbBlack, kPairBlack, kAosOut };
 hipError_t launch_constrained(const DevLattice& d, int step, const double eC[3], double T, hipStream_t s,
                               int64_t* blocks);
+// The finalize of a constrained sweep (pair records of rec_blocks rows per
+// colour, flags fin) together with the colour-0 records of the next sweep.
+hipError_t launch_finalize_nbsum(const DevLattice& d, int64_t rec_blocks, int fin, double T, hipStream_t s);
 hipError_t launch_measure(const DevLattice& d, hipStream_t s, int64_t* blocks);
 // Mean spin of each z plane into out[3*nz] (device memory).
 hipError_t launch_plane_means(const DevLattice& d, double* out, hipStream_t s);

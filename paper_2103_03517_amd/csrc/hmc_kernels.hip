@@ -119,13 +119,14 @@ __device__ __forceinline__ void gather_neighbours(const KArgs<R>& a, const Array
 
 // ---------------------------------------------------------------------------
 // Constrained sweep (Table A2).  A constrained call works on an AoS copy of
-// the spins (one 16-byte FP32 / 32-byte FP64 entry per site, both colours),
-// made on entry and copied back on exit, so that a random gather is one
-// cache line instead of three.  Before each colour pass the neighbour sums of
-// that colour are precomputed (the other colour does not change during the
-// pass, so they are exact); the pair pass then needs, for each spin of a
-// pair, its own entry and its neighbour sum: two lines for the random
-// partner instead of twenty-one.
+// the spins (one 4-vector per site, both colours), made on entry and copied
+// back on exit.  Before each colour's pair pass a stencil kernel writes, for
+// every site of that colour in site order, a record of its spin and the sum
+// of its six neighbours (32 bytes FP32, 64 FP64; the other colour does not
+// change during the pass, so the sums are exact).  A pair then needs its two
+// records -- the first read in site order, the partner's at a random
+// address, the pairing being a random permutation: one cache line per pair
+// instead of seven sites -- and writes its new spins into the AoS copy.
 // ---------------------------------------------------------------------------
 template <typename R> struct Vec4T;
 template <> struct Vec4T<float> { using type = float4; };
@@ -133,22 +134,34 @@ template <> struct Vec4T<double> { using type = double4; };
 template <typename R> using Vec4 = typename Vec4T<R>::type;
 
 template <typename R>
-__device__ __forceinline__ V3<R> ld4(const Vec4<R>* p, uint32_t i)
+struct Rec {
+    Vec4<R> s;    // spin (w unused)
+    Vec4<R> nb;   // sum of the six neighbours (other colour)
+};
+
+template <typename R>
+__device__ __forceinline__ V3<R> v3(const Vec4<R>& q)
 {
-    const Vec4<R> q = p[i];
     return V3<R>{q.x, q.y, q.z};
 }
 
 template <typename R>
-__device__ __forceinline__ void st4(Vec4<R>* p, uint32_t i, const V3<R>& v)
+__device__ __forceinline__ Vec4<R> v4(const V3<R>& v)
 {
     Vec4<R> q;
     q.x = v.x;
     q.y = v.y;
     q.z = v.z;
     q.w = R(0);
-    p[i] = q;
+    return q;
 }
+
+#ifndef HMC_PAIR_BLOCKS
+#define HMC_PAIR_BLOCKS 512      // most work-groups of the pair pass
+#endif
+#ifndef HMC_NB_BLOCKS
+#define HMC_NB_BLOCKS 2048       // most work-groups of the record stencil
+#endif
 
 // SoA -> AoS (to_aos) or AoS -> SoA, both colours; aos[c * Nc + k].
 template <typename R, bool TO_AOS>
@@ -157,14 +170,14 @@ __global__ __launch_bounds__(kThreads) void aos_copy_kernel(const KArgs<R> a, Ve
     const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
     const int c = blockIdx.y;
     if (k >= a.Nc) return;
-    const size_t i = (size_t)c * a.Nc + k;
+    Vec4<R>* q = aos + (size_t)c * a.Nc + k;
     if (TO_AOS) {
-        st4<R>(aos + (size_t)c * a.Nc, k, V3<R>{a.s[c][0][k], a.s[c][1][k], a.s[c][2][k]});
+        *q = v4<R>(V3<R>{a.s[c][0][k], a.s[c][1][k], a.s[c][2][k]});
     } else {
-        const Vec4<R> q = aos[i];
-        a.s[c][0][k] = q.x;
-        a.s[c][1][k] = q.y;
-        a.s[c][2][k] = q.z;
+        const Vec4<R> v = *q;
+        a.s[c][0][k] = v.x;
+        a.s[c][1][k] = v.y;
+        a.s[c][2][k] = v.z;
     }
 }
 
@@ -190,18 +203,21 @@ __device__ __forceinline__ void neighbour_indices(uint32_t k, uint32_t hx, uint3
     zp_wraps = z == nz - 1;
 }
 
-// Neighbour sums of colour C (from the AoS copy of the other colour).
+// Records of colour C over work-groups b, b + count, ... of the launch:
+// site k's spin and the sum of its neighbours (the other colour's AoS spins).
 template <typename R, int C>
-__global__ __launch_bounds__(kThreads) void nbsum_kernel(const KArgs<R> a, const Vec4<R>* aos, Vec4<R>* nbs)
+__device__ __forceinline__ void records_range(const KArgs<R>& a, const Vec4<R>* aos, Rec<R>* rec, uint32_t b,
+                                              uint32_t count)
 {
     const Vec4<R>* other = aos + (size_t)(1 - C) * a.Nc;
-    for (uint32_t k = blockIdx.x * kThreads + threadIdx.x; k < a.Nc; k += gridDim.x * kThreads) {
+    const Vec4<R>* own = aos + (size_t)C * a.Nc;
+    for (uint32_t k = b * kThreads + threadIdx.x; k < a.Nc; k += count * kThreads) {
         uint32_t id[6];
         bool wm, wp;
         neighbour_indices<C>(k, a.hx, a.ny, a.nz, a.P, id, wm, wp);
         V3<R> v[6];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) v[i] = ld4<R>(other, id[i]);
+        for (int i = 0; i < 6; ++i) v[i] = v3<R>(other[id[i]]);
         if (a.zbound) {
             if (wm) v[4] = across_z(v[4], a.zbound);
             if (wp) v[5] = across_z(v[5], a.zbound);
@@ -215,81 +231,214 @@ __global__ __launch_bounds__(kThreads) void nbsum_kernel(const KArgs<R> a, const
         const V3<R> nb{((((v[0].x + v[1].x) + v[2].x) + v[3].x) + v[4].x) + v[5].x,
                        ((((v[0].y + v[1].y) + v[2].y) + v[3].y) + v[4].y) + v[5].y,
                        ((((v[0].z + v[1].z) + v[2].z) + v[3].z) + v[4].z) + v[5].z};
-        st4<R>(nbs, k, nb);
+        Rec<R> r;
+        r.s = own[k];
+        r.nb = v4<R>(nb);
+        rec[k] = r;
+    }
+}
+
+template <typename R, int C>
+__global__ __launch_bounds__(kThreads) void records_kernel(const KArgs<R> a, const Vec4<R>* aos, Rec<R>* rec)
+{
+    records_range<R, C>(a, aos, rec, blockIdx.x, gridDim.x);
+}
+
+// The end of one constrained sweep and the start of the next in one launch:
+// work-group 0 runs the per-sweep finalize (the records of the two pair
+// passes, nrec rows each), the others write the colour-0 records of the next
+// sweep, which need only the spins.  The finalize and the records touch
+// disjoint memory, so the finalize runs in the shadow of the stencil.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void finalize_records_kernel(const KArgs<R> a, const Vec4<R>* aos, Rec<R>* rec,
+                                                                    uint32_t nrec, int fin, double T, double N)
+{
+    __shared__ double scratch[5 * (kNumPart + 1)];
+    if (blockIdx.x == 0) {
+        finalize_body(a.st, a.part, a.cnt, a.cnt_stride, nrec, nrec, 2 * nrec, fin, T, N, scratch);
+        return;
+    }
+    records_range<R, 0>(a, aos, rec, blockIdx.x - 1, gridDim.x - 1);
+}
+
+// Feistel domain of the shuffle of N_c indices: 2*half bits, the smallest
+// even width covering N_c.
+struct Shuffle {
+    uint32_t half, mask;
+};
+
+static inline Shuffle shuffle_for(uint32_t n)
+{
+    uint32_t bits = 2;
+    while (bits < 32 && (1ull << bits) < n) bits += 2;
+    Shuffle f;
+    f.half = bits / 2;
+    f.mask = f.half >= 32 ? 0xFFFFFFFFu : ((1u << f.half) - 1u);
+    return f;
+}
+
+// Per-sweep constants of a pair pass.
+template <typename R>
+struct PairCtx {
+    Model<R> m;
+    V3<R> ec;
+    R c1, scale, invML;
+    double ML;
+    uint32_t sweep, inst, key0, key1;
+};
+
+// The pair move of Table A2 on pair k = (i, j) of colour C, with the records
+// ri, rj of its two spins: cone move of S_i, compensation of the transverse
+// change by S_j (perpendicular to eC; the parallel part from the length),
+// M_L ratio and Jacobian, Metropolis test with exp(-(dE_i + dE_j)/T); on
+// acceptance both new spins go to the AoS copy.  OBS adds the one-site terms
+// of both final spins (and in the black pass their exchange with their final
+// red neighbours).
+template <typename R, int C, bool OBS>
+__device__ __forceinline__ void pair_move(const PairCtx<R>& x, Vec4<R>* own, uint32_t k, uint32_t ia, uint32_t ja,
+                                          const Rec<R>& ri, const Rec<R>& rj, uint32_t& nacc, Acc& acc)
+{
+    const Model<R>& m = x.m;
+    const V3<R>& ec = x.ec;
+    const V3<R> si = v3<R>(ri.s), nbi = v3<R>(ri.nb);
+    const V3<R> sj = v3<R>(rj.s), nbj = v3<R>(rj.nb);
+    const Rand4 rn = philox(x.sweep, k, 2u + (uint32_t)C, x.inst, x.key0, x.key1);
+    const V3<R> ti = cone_move(si, Prim<R>::u01(rn.r0), Prim<R>::u01(rn.r1), x.c1);
+
+    const R pi_old = dot(si, ec), pi_new = dot(ti, ec), pj_old = dot(sj, ec);
+    V3<R> pj;
+    pj.x = (sj.x - pj_old * ec.x) + (si.x - pi_old * ec.x) - (ti.x - pi_new * ec.x);
+    pj.y = (sj.y - pj_old * ec.y) + (si.y - pi_old * ec.y) - (ti.y - pi_new * ec.y);
+    pj.z = (sj.z - pj_old * ec.z) + (si.z - pi_old * ec.z) - (ti.z - pi_new * ec.z);
+    const R q = dot(sj, sj) - dot(pj, pj);
+    bool ok = q > R(0);
+    const R pj_new = (pj_old >= R(0) ? R(1) : R(-1)) * Prim<R>::sqrt_(ok ? q : R(1));
+    const V3<R> tj{pj.x + pj_new * ec.x, pj.y + pj_new * ec.y, pj.z + pj_new * ec.z};
+    // (M_L'/M_L)^2 with M_L' = |M_L| + change along eC
+    const R xr = ((pi_new + pj_new) - pi_old - pj_old) * x.invML;
+    ok = ok && (R(1) + xr > R(0)) && (x.ML != 0.0);
+    const V3<R> hi{m.J * nbi.x + m.h.x, m.J * nbi.y + m.h.y, m.J * nbi.z + m.h.z};
+    const V3<R> hj{m.J * nbj.x + m.h.x, m.J * nbj.y + m.h.y, m.J * nbj.z + m.h.z};
+    const R dE = delta_e(m, si, ti, hi) + delta_e(m, sj, tj, hj);
+    const R ratio = (R(1) + xr) * (R(1) + xr) * fabs(pj_old / pj_new);
+    ok = ok && (Prim<R>::u01(rn.r2) < ratio * Prim<R>::boltzmann(dE, x.scale));
+    const V3<R> fi = ok ? ti : si;
+    const V3<R> fj = ok ? tj : sj;
+    if (ok) {
+        own[ia] = v4<R>(ti);
+        own[ja] = v4<R>(tj);
+        nacc += 2;
+    }
+    if (OBS) {
+        if (C == 1) acc.ex += (double)(-m.J * dot(fi, nbi)) + (double)(-m.J * dot(fj, nbj));
+        add_site<R, true>(acc, m, fi);
+        add_site<R, true>(acc, m, fj);
     }
 }
 
 // Pair pass of colour C.  The shuffled order pi of the colour indices is a
 // keyed bijection evaluated inline (nothing is stored); pair k is
-// (pi(2k), pi(2k+1)).  One thread per colour index a: the thread whose a is
-// the first spin of its pair (pi^-1(a) even) runs the pair move, so the
-// first spin is read coalesced and only the partner is a random gather.  M_L
-// is the moment along eC at the start of the sweep (one value for both
-// colours, as in the paper).  OBS adds the one-site terms (moment,
-// anisotropy, Zeeman, torque) of both final spins of every pair, and in the
-// black pass also their exchange with their final red neighbours; since pi
-// is a bijection every site is covered once, and every bond once through its
-// black end.  Results go to row part_base + block (red pass: rows 0 .., black
-// pass: rows grid ..).
+// (pi(2k), pi(2k+1)) (N_c is even: nx and ny are).  A work-group scans tiles
+// of 2 x 256 consecutive colour indices a; a is the first spin of pair
+// pi^-1(a)/2 when pi^-1(a) is even, and such pairs are queued in LDS in scan
+// order (wave ballots, waves in order), so the queue never depends on
+// scheduling.  The queue is drained in rounds of 256 pairs, one per thread,
+// and what is left of it carries over to the next tile: every lane runs a
+// pair move, and the first record of each pair is read near site order (only
+// the partner's is a random gather).  M_L is the moment along eC at the
+// start of the sweep (one value for both colours, as in the paper).  OBS adds
+// the one-site terms of both final spins of every pair; since pi is a
+// bijection every site is covered once, and in the black pass every bond once
+// through its black end.  Results go to row part_base + block (red pass: rows
+// 0 .., black pass: rows grid ..).
 template <typename R, int C, bool OBS>
-__global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R>* aos, const Vec4<R>* nbs,
-                                                        const V3<R> ec, const uint32_t half, const uint32_t mask,
-                                                        const R scale, const uint32_t part_base)
+__global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R>* aos, const Rec<R>* rec,
+                                                        const V3<R> ec, const Shuffle f, const R scale,
+                                                        const uint32_t part_base)
 {
+    constexpr uint32_t kTrip = 2 * kThreads;                 // indices scanned per tile
+    constexpr uint32_t kQueue = kTrip + kThreads;            // at most 255 carried + 512 new
+    constexpr int kWaves = kThreads / 64;
     __shared__ double scratch[5 * kNumPart];
+    __shared__ uint32_t qa[kQueue], qj[kQueue], qk[kQueue];
+    __shared__ uint32_t wcnt[kWaves];
     Vec4<R>* own = aos + (size_t)C * a.Nc;
-    const uint32_t sweep = (uint32_t)a.st->sweep;
-    const R c1 = a.c1tab[a.st->theta];
-    const Model<R> m = a.m;
+    PairCtx<R> x;
+    x.m = a.m;
+    x.ec = ec;
+    x.sweep = (uint32_t)a.st->sweep;
+    x.c1 = a.c1tab[a.st->theta];
+    x.scale = scale;
     const double* M = a.st->M;
-    const double ML = M[0] * (double)ec.x + M[1] * (double)ec.y + M[2] * (double)ec.z;
-    const R invML = (R)(1.0 / fabs(ML));
-    const Rand4 key = philox(sweep, 0u, 5u + (uint32_t)C, a.inst, a.key0, a.key1);
+    x.ML = M[0] * (double)ec.x + M[1] * (double)ec.y + M[2] * (double)ec.z;
+    x.invML = (R)(1.0 / fabs(x.ML));
+    x.inst = a.inst;
+    x.key0 = a.key0;
+    x.key1 = a.key1;
+    const Rand4 key = philox(x.sweep, 0u, 5u + (uint32_t)C, a.inst, a.key0, a.key1);
 
+    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint32_t tiles = (a.Nc + kTrip - 1u) / kTrip;
     uint32_t nacc = 0;
     Acc acc;
-    for (uint32_t ia = blockIdx.x * kThreads + threadIdx.x; ia < a.Nc; ia += gridDim.x * kThreads) {
-        const uint32_t pos = unshuffle_index(ia, a.Nc, half, mask, key);
-        if ((pos & 1u) == 0u) {
-            const uint32_t k = pos >> 1;
-            const uint32_t ja = shuffle_index(pos + 1u, a.Nc, half, mask, key);
-            const V3<R> si = ld4<R>(own, ia), nbi = ld4<R>(nbs, ia);
-            const V3<R> sj = ld4<R>(own, ja), nbj = ld4<R>(nbs, ja);
-            const Rand4 rn = philox(sweep, k, 2u + (uint32_t)C, a.inst, a.key0, a.key1);
-            const V3<R> ti = cone_move(si, Prim<R>::u01(rn.r0), Prim<R>::u01(rn.r1), c1);
-
-            // compensation of the transverse change, along/perpendicular to eC
-            const R pi_old = dot(si, ec), pi_new = dot(ti, ec), pj_old = dot(sj, ec);
-            V3<R> pj;
-            pj.x = (sj.x - pj_old * ec.x) + (si.x - pi_old * ec.x) - (ti.x - pi_new * ec.x);
-            pj.y = (sj.y - pj_old * ec.y) + (si.y - pi_old * ec.y) - (ti.y - pi_new * ec.y);
-            pj.z = (sj.z - pj_old * ec.z) + (si.z - pi_old * ec.z) - (ti.z - pi_new * ec.z);
-            const R q = dot(sj, sj) - dot(pj, pj);
-            bool ok = q > R(0);
-            const R pj_new = (pj_old >= R(0) ? R(1) : R(-1)) * Prim<R>::sqrt_(ok ? q : R(1));
-            const V3<R> tj{pj.x + pj_new * ec.x, pj.y + pj_new * ec.y, pj.z + pj_new * ec.z};
-            // (M_L'/M_L)^2 with M_L' = |M_L| + change along eC
-            const R xr = ((pi_new + pj_new) - pi_old - pj_old) * invML;
-            ok = ok && (R(1) + xr > R(0)) && (ML != 0.0);
-            const V3<R> hi{m.J * nbi.x + m.h.x, m.J * nbi.y + m.h.y, m.J * nbi.z + m.h.z};
-            const V3<R> hj{m.J * nbj.x + m.h.x, m.J * nbj.y + m.h.y, m.J * nbj.z + m.h.z};
-            const R dE = delta_e(m, si, ti, hi) + delta_e(m, sj, tj, hj);
-            const R ratio = (R(1) + xr) * (R(1) + xr) * fabs(pj_old / pj_new);
-            ok = ok && (Prim<R>::u01(rn.r2) < ratio * Prim<R>::boltzmann(dE, scale));
-            const V3<R> fi = ok ? ti : si;
-            const V3<R> fj = ok ? tj : sj;
-            if (ok) {
-                st4<R>(own, ia, ti);
-                st4<R>(own, ja, tj);
-                nacc += 2;
+    uint32_t held = 0;                                       // queued pairs, the same in every thread
+    for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+#pragma unroll
+        for (uint32_t u = 0; u < kTrip / kThreads; ++u) {
+            const uint32_t ia = tile * kTrip + u * kThreads + t;
+            bool first = false;
+            uint32_t ja = 0, k = 0;
+            if (ia < a.Nc) {
+                const uint32_t pos = unshuffle_index(ia, a.Nc, f.half, f.mask, key);
+                first = (pos & 1u) == 0u;
+                if (first) {
+                    ja = shuffle_index(pos + 1u, a.Nc, f.half, f.mask, key);
+                    k = pos >> 1;
+                }
             }
-            if (OBS) {
-                if (C == 1) acc.ex += (double)(-m.J * dot(fi, nbi)) + (double)(-m.J * dot(fj, nbj));
-                add_site<R, true>(acc, m, fi);
-                add_site<R, true>(acc, m, fj);
+            const uint64_t ball = __ballot(first);
+            if (lane == 0) wcnt[wave] = (uint32_t)__popcll(ball);
+            __syncthreads();
+            uint32_t off = held, total = held;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                off += (uint32_t)w < wave ? wcnt[w] : 0u;
+                total += wcnt[w];
             }
+            if (first) {
+                const uint32_t e = off + (uint32_t)__popcll(ball & below);
+                qa[e] = ia;
+                qj[e] = ja;
+                qk[e] = k;
+            }
+            held = total;
+            __syncthreads();
         }
+        uint32_t done = 0;
+        for (; held - done >= kThreads; done += kThreads) {
+            const uint32_t e = done + t;
+            const uint32_t ia = qa[e], ja = qj[e];
+            pair_move<R, C, OBS>(x, own, qk[e], ia, ja, rec[ia], rec[ja], nacc, acc);
+        }
+        // the rest of the queue (fewer than 256 pairs) to its front
+        const uint32_t rest = held - done;
+        uint32_t ca = 0, cj = 0, ck = 0;
+        if (t < rest) {
+            ca = qa[done + t];
+            cj = qj[done + t];
+            ck = qk[done + t];
+        }
+        __syncthreads();
+        if (t < rest) {
+            qa[t] = ca;
+            qj[t] = cj;
+            qk[t] = ck;
+        }
+        held = rest;
+        __syncthreads();
     }
+    if (t < held) pair_move<R, C, OBS>(x, own, qk[t], qa[t], qj[t], rec[qa[t]], rec[qj[t]], nacc, acc);
     KArgs<R> ra = a;
     ra.part = a.part + (size_t)part_base * kNumPart;
     block_end<R, OBS>(ra, C, blockIdx.x, nacc, acc, scratch);
@@ -391,35 +540,28 @@ static void constrained_go(const DevLattice& d, int step, const double eC[3], do
 {
     const auto a = make_args<R>(d);
     Vec4<R>* aos = static_cast<Vec4<R>*>(d.aos);
-    Vec4<R>* nbs = static_cast<Vec4<R>*>(d.nbs);
+    Rec<R>* rec = reinterpret_cast<Rec<R>*>(aos + 2 * (size_t)d.Nc);
     const uint32_t n = (uint32_t)d.Nc;
     const uint32_t full = cdiv(n, kThreads);
-    const uint32_t grid = full < (uint32_t)kGatherBlocks ? full : (uint32_t)kGatherBlocks;
-    *blocks = grid;
+    const uint32_t tiles = cdiv(n, 2u * kThreads);
+    const uint32_t pgrid = tiles < (uint32_t)HMC_PAIR_BLOCKS ? tiles : (uint32_t)HMC_PAIR_BLOCKS;
+    const uint32_t ngrid = full < (uint32_t)HMC_NB_BLOCKS ? full : (uint32_t)HMC_NB_BLOCKS;
+    *blocks = pgrid;
     if (step == kAosIn) {
         aos_copy_kernel<R, true><<<dim3(full, 2), kThreads, 0, s>>>(a, aos);
-        return;
-    }
-    if (step == kAosOut) {
+    } else if (step == kAosOut) {
         aos_copy_kernel<R, false><<<dim3(full, 2), kThreads, 0, s>>>(a, aos);
-        return;
+    } else if (step == kNbRed) {
+        records_kernel<R, 0><<<ngrid, kThreads, 0, s>>>(a, aos, rec);
+    } else if (step == kNbBlack) {
+        records_kernel<R, 1><<<ngrid, kThreads, 0, s>>>(a, aos, rec);
+    } else {
+        const V3<R> ec{(R)eC[0], (R)eC[1], (R)eC[2]};
+        const R scale = Prim<R>::scale_for(T);
+        const Shuffle f = shuffle_for(n);
+        if (step == kPairRed) pair_kernel<R, 0, true><<<pgrid, kThreads, 0, s>>>(a, aos, rec, ec, f, scale, 0u);
+        else pair_kernel<R, 1, true><<<pgrid, kThreads, 0, s>>>(a, aos, rec, ec, f, scale, pgrid);
     }
-    if (step == kNbRed) {
-        nbsum_kernel<R, 0><<<full, kThreads, 0, s>>>(a, aos, nbs);
-        return;
-    }
-    if (step == kNbBlack) {
-        nbsum_kernel<R, 1><<<full, kThreads, 0, s>>>(a, aos, nbs);
-        return;
-    }
-    uint32_t bits = 2;
-    while (bits < 32 && (1ull << bits) < n) bits += 2;
-    const uint32_t half = bits / 2;
-    const uint32_t mask = half >= 32 ? 0xFFFFFFFFu : ((1u << half) - 1u);
-    const V3<R> ec{(R)eC[0], (R)eC[1], (R)eC[2]};
-    const R scale = Prim<R>::scale_for(T);
-    if (step == kPairRed) pair_kernel<R, 0, true><<<grid, kThreads, 0, s>>>(a, aos, nbs, ec, half, mask, scale, 0u);
-    else pair_kernel<R, 1, true><<<grid, kThreads, 0, s>>>(a, aos, nbs, ec, half, mask, scale, grid);
 }
 
 hipError_t launch_constrained(const DevLattice& d, int step, const double eC[3], double T, hipStream_t s,
@@ -427,6 +569,24 @@ hipError_t launch_constrained(const DevLattice& d, int step, const double eC[3],
 {
     if (d.precision == 32) constrained_go<float>(d, step, eC, T, s, blocks);
     else constrained_go<double>(d, step, eC, T, s, blocks);
+    return hipGetLastError();
+}
+
+template <typename R>
+static void finalize_records_go(const DevLattice& d, int64_t rec_blocks, int fin, double T, hipStream_t s)
+{
+    Vec4<R>* aos = static_cast<Vec4<R>*>(d.aos);
+    const uint32_t full = cdiv((uint64_t)d.Nc, kThreads);
+    const uint32_t ngrid = 1u + (full < (uint32_t)HMC_NB_BLOCKS ? full : (uint32_t)HMC_NB_BLOCKS);
+    finalize_records_kernel<R><<<ngrid, kThreads, 0, s>>>(make_args<R>(d), aos,
+                                                          reinterpret_cast<Rec<R>*>(aos + 2 * (size_t)d.Nc),
+                                                          (uint32_t)rec_blocks, fin, T, (double)d.N);
+}
+
+hipError_t launch_finalize_nbsum(const DevLattice& d, int64_t rec_blocks, int fin, double T, hipStream_t s)
+{
+    if (d.precision == 32) finalize_records_go<float>(d, rec_blocks, fin, T, s);
+    else finalize_records_go<double>(d, rec_blocks, fin, T, s);
     return hipGetLastError();
 }
 
