@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 
 METRIC = "spin updates/sec at 256³ (FP32 vs FP64); batched M(T) jobs/s + p99 latency"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, public specification
+MIN_WARMUP = 200                 # untimed sweeps before a timed region, at least
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_256cubed_fp32_traffic.md")
 # everything that decides the machine code of the colour pass: its source,
 # the headers it includes and the compiler flags
@@ -140,7 +141,9 @@ def time_leg(H, torch, shape, precision, T, steps, warmup, constrained=False, la
                 g.sweep(T, c, sample=True)
             done += c
 
-    run(warmup)
+    # warm-up: the W steps asked for, and at least MIN_WARMUP sweeps in all,
+    # so that a short timed region does not see the clocks still ramping
+    run(max(warmup, MIN_WARMUP))
     # timed region: K steps, nothing else on the stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -250,36 +253,41 @@ def batch_leg(sequential=False, tail=12000):
 
 
 def serve_leg(rate=20.0, seconds=10.0):
-    """Poisson arrivals (seed 5) of m(T) jobs on 32^3..192^3 lattices, 200 +
-    800 sweeps each, served by the continuous-batching loop in FP32; then the
+    """Poisson arrivals (seed 5) of a mixed job stream served by the
+    continuous-batching loop in FP32: 60 % m(T) jobs (32^3..192^3, 200 + 800
+    sweeps), 15 % domain-wall jobs (64 x 64 x 512, 1000 + 1000), 15 %
+    constrained anisotropy jobs (32^3..64^3, Kc = 0.05, 500 + 500), 10 %
+    granular films (1024^2 x {5, 10, 15}, grains 8..24, 200 + 800); then the
     same jobs all at once (saturation) for the capacity in jobs/s."""
     from paper_2103_03517_amd import serving as S
-    jobs = S.poisson_jobs(rate, seconds, wall_fraction=0.2)
+    mix = dict(wall_fraction=0.15, aniso_fraction=0.15, film_fraction=0.1)
+    jobs = S.poisson_jobs(rate, seconds, **mix)
     srv = S.Server(precision=32, hbm_budget=32 << 30, quantum=50)
-    log(f"leg 6: serving {len(jobs)} m(T) jobs arriving at {rate}/s over {seconds} s")
-    shapes = srv.tune_shapes(sorted({j.shape for j in jobs}))
+    kinds = {k: sum(j.kind == k for j in jobs) for k in S.KINDS}
+    log(f"leg 6: serving {len(jobs)} jobs {kinds} arriving at {rate}/s over {seconds} s")
+    shapes = srv.tune_shapes(sorted({j.shape for j in jobs if j.batched}))
     done = srv.run(jobs)
     live = S.latency_summary(done)
-    log(f"  p50 {live['p50_s'] * 1e3:.1f} ms, p99 {live['p99_s'] * 1e3:.1f} ms, "
-        f"max active {srv.stats['max_active']}")
+    log(f"  p50 {live['p50_s'] * 1e3:.1f} ms, p99 {live['p99_s'] * 1e3:.1f} ms, max active "
+        f"{srv.stats['max_active']}, by kind {live['by_kind']}, host phases {srv.phase_s}")
     sat = S.Server(precision=32, hbm_budget=32 << 30, quantum=50, shapes=shapes)
-    done2 = sat.run(S.poisson_jobs(rate, seconds, wall_fraction=0.2), realtime=False)
+    done2 = sat.run(S.poisson_jobs(rate, seconds, **mix), realtime=False)
     cap = S.latency_summary(done2)
     log(f"  saturation: {cap['jobs_per_s']:.1f} jobs/s, {cap['updates_per_s'] / 1e9:.1f} G updates/s")
-    import numpy as np
-    walls = [j for j in done if j.kind == "wall"]
-    return {"workload": f"Poisson arrivals at {rate}/s for {seconds} s (seed 5): 80% m(T) jobs on edge^3 "
-                        "periodic lattices, edge uniform in {32,48,64,96,128,160,192}, T ~ U(0.05, 1.7), "
-                        "200 equilibration + 800 sampled sweeps (blocks of 100); 20% domain-wall jobs on "
-                        "64x64x512 anti-periodic along z, T ~ U(0.05, 1.2), 1000 + 1000 sweeps, profile "
-                        "fitted every 100; Ku=0.01, FP32, HBM budget 32 GiB, at most 64 jobs in flight",
-            "wall_jobs": len(walls),
-            "wall_p99_latency_s": (float(np.percentile([j.finished - j.arrival for j in walls], 99))
-                                   if walls else None),
-            "offered_jobs": len(jobs), "completed": live["jobs"],
+    return {"workload": f"Poisson arrivals at {rate}/s for {seconds} s (seed 5): 60% m(T) jobs on edge^3 "
+                        "periodic lattices, edge uniform in {32,48,64,96,128,160,192}, T ~ U(0.05, 1.7), 200 + "
+                        "800 sampled sweeps (blocks of 100); 15% domain-wall jobs on 64x64x512 anti-periodic along "
+                        "z, T ~ U(0.05, 1.2), 1000 + 1000 sweeps, profile every 100; 15% constrained anisotropy "
+                        "jobs on 32^3/48^3/64^3, Kc=0.05, e_C at theta 0..90 by 10 and phi 0/45, T ~ U(0.2, 1.4), "
+                        "500 + 500 constrained sweeps; 10% granular films 1024^2 x {5,10,15} open along z, Voronoi "
+                        "grains of diameter 8/16/24, T ~ U(0.05, 1.4), 200 + 800 sweeps; Ku=0.01, FP32, HBM "
+                        "budget 32 GiB, at most 64 jobs in flight",
+            "offered_jobs": len(jobs), "jobs_by_kind": kinds, "completed": live["jobs"],
             "p50_latency_s": live["p50_s"], "p99_latency_s": live["p99_s"], "max_latency_s": live["max_s"],
+            "latency_by_kind": live["by_kind"],
             "jobs_per_s": live["jobs_per_s"], "max_active": srv.stats["max_active"],
             "ticks": srv.stats["ticks"], "batch_rebuilds": srv.stats["rebuilds"],
+            "snapshots": srv.stats["snapshots"],
             "host_phase_s": {k: round(v, 3) for k, v in srv.phase_s.items()},
             "saturation_jobs_per_s": cap["jobs_per_s"], "saturation_updates_per_s": cap["updates_per_s"],
             "saturation_p99_latency_s": cap["p99_s"]}
@@ -356,6 +364,7 @@ def main():
     ap.add_argument("--main-only", action="store_true", help="only the 256^3 FP32 leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-jobs leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving leg (no JSON line)")
     ap.add_argument("--batch-sequential", action="store_true",
                     help="also run the batched jobs one lattice at a time, for comparison")
     ap.add_argument("--profile-pass", action="store_true",
@@ -402,6 +411,10 @@ def main():
         g.sweep(1.0, 10, sample=True)
         torch.cuda.synchronize()
         log("profile-deep: 10 sampled 384^3 FP32 sweeps (20 colour passes, two planes of look-ahead)")
+        return
+    if args.serve_only:
+        import json as _j
+        print(_j.dumps(serve_leg()), flush=True)
         return
     if args.profile_constrained:
         g = H.Lattice(128, 128, 128, precision=32, J=1.0, Kc=0.05, seed=7, init="aligned",
@@ -501,6 +514,7 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
+        "warmup_sweeps_run": max(W, MIN_WARMUP),
         "ms_per_step": main_leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",

@@ -143,7 +143,8 @@ size_t hmc_workspace_bytes(const hmc_params* p);
  * aligned, at least hmc_workspace_bytes(p) bytes, owned by the caller)
  * and enqueues the initial state (init == 0: along init_dir; init == 1:
  * uniform on the sphere from Philox tag 4) on hip_stream (a hipStream_t,
- * NULL for the default stream).  On success *out receives the handle.
+ * NULL for the default stream), without waiting for it (nothing is copied
+ * from host memory).  On success *out receives the handle.
  * Errors: HMC_EINVAL, HMC_EDIM, HMC_ENOMEM, HMC_EHIP. */
 int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes,
                      void* hip_stream, hmc_lattice** out);
@@ -189,6 +190,15 @@ int hmc_reset_stats(hmc_lattice* L);
  * not carry them.  Synchronises.  Errors: HMC_EINVAL (no masks, asymmetric
  * or out-of-range bits), HMC_ENOMEM, HMC_EHIP. */
 int hmc_set_bond_masks(hmc_lattice* L, const uint8_t* host_mask);
+
+/* As hmc_set_bond_masks, without waiting: the masks are copied from
+ * host_mask on the lattice's stream, so host_mask must stay valid and
+ * unchanged until the stream has passed the call (pinned host memory keeps
+ * the copy asynchronous).  check != 0 runs the symmetry check first (on the
+ * host, before anything is enqueued); check == 0 skips it, for masks already
+ * checked (the same masks given to another lattice of the same shape).
+ * Errors: HMC_EINVAL, HMC_EHIP. */
+int hmc_set_bond_masks_async(hmc_lattice* L, const uint8_t* host_mask, int32_t check);
 
 /* Mean spin of every z plane (a slice of nx*ny sites, both colours) of the
  * current spins: host_out receives 3*nz doubles, plane z at 3z .. 3z+2.  The
@@ -268,6 +278,31 @@ int hmc_read_timing(hmc_lattice* L, hmc_timing* out);
 int hmc_measure_static(const hmc_params* p, const void* dev_spins, size_t spins_bytes, void* hip_stream,
                        hmc_obs* out);
 
+/* Asynchronous reads, for loops that keep the device busy while the host
+ * admits and retires work (continuous batching).  A snapshot is the chain
+ * state of a lattice -- counters and the accumulators of Eq. 6 -- as the
+ * stream reaches the call: hmc_snapshot_enqueue enqueues, for lattice i of
+ * lattices[0 .. count-1] (all on one stream), a copy of its state into
+ * host_dst + i * hmc_snapshot_bytes() and returns at once.  host_dst should
+ * be pinned host memory (hipHostMalloc, or a pinned torch tensor) so that the
+ * copies do not block; it is valid once the stream has passed the call (an
+ * event recorded after it has completed).  hmc_snapshot_observables fills
+ * *out from one such record of a lattice of n spins and the given precision,
+ * as hmc_observables would from the accumulators (the instantaneous fields
+ * are those of the last sampled or constrained sweep, not a fresh
+ * measurement); it returns HMC_ENUMERIC, with *out filled, if the record
+ * carries the non-finite flag.  Errors: HMC_EINVAL, HMC_EHIP. */
+size_t hmc_snapshot_bytes(void);
+int hmc_snapshot_enqueue(hmc_lattice* const* lattices, int32_t count, void* host_dst);
+int hmc_snapshot_observables(const void* record, int64_t n, int32_t precision, hmc_obs* out);
+
+/* As hmc_plane_means, into 3*nz doubles of device memory at dev_out (owned
+ * by the caller), enqueued on the lattice's stream without waiting. */
+int hmc_plane_means_async(hmc_lattice* L, double* dev_out);
+
+/* Releases the handle.  Work already enqueued for the lattice is not
+ * waited for (launches copy their arguments); the workspace must stay valid
+ * until that work has run. */
 void hmc_destroy(hmc_lattice* L);
 const char* hmc_strerror(int status);
 const char* hmc_last_error(const hmc_lattice* L);

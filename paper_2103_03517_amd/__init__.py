@@ -12,7 +12,7 @@ import os
 import numpy as np
 import torch
 
-__all__ = ["Lattice", "Batch", "HmcError", "lib", "measure_static", "LIB_PATH", "SYMBOLS"]
+__all__ = ["Lattice", "Batch", "Snapshot", "HmcError", "lib", "measure_static", "LIB_PATH", "SYMBOLS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhmc.so")
@@ -66,7 +66,8 @@ SYMBOLS = ("hmc_workspace_bytes", "hmc_init_lattice", "hmc_sweep", "hmc_constrai
            "hmc_batch_read_timing", "hmc_batch_destroy", "hmc_batch_last_error",
            "hmc_batch_observables", "hmc_batch_reset_stats", "hmc_batch_sweep_each",
            "hmc_batch_set_lattices", "hmc_batch_set_chunk_bytes", "hmc_batch_get_chunk_bytes",
-           "hmc_measure_static")
+           "hmc_measure_static", "hmc_snapshot_bytes", "hmc_snapshot_enqueue", "hmc_snapshot_observables",
+           "hmc_plane_means_async", "hmc_set_bond_masks_async")
 
 _lib = None
 
@@ -155,6 +156,16 @@ def lib():
     L.hmc_batch_get_chunk_bytes.argtypes = [vp, P(ctypes.c_int64)]
     L.hmc_measure_static.restype = i32
     L.hmc_measure_static.argtypes = [P(Params), vp, ctypes.c_size_t, vp, P(Obs)]
+    L.hmc_snapshot_bytes.restype = ctypes.c_size_t
+    L.hmc_snapshot_bytes.argtypes = []
+    L.hmc_snapshot_enqueue.restype = i32
+    L.hmc_snapshot_enqueue.argtypes = [P(vp), i32, vp]
+    L.hmc_snapshot_observables.restype = i32
+    L.hmc_snapshot_observables.argtypes = [vp, ctypes.c_int64, i32, P(Obs)]
+    L.hmc_set_bond_masks_async.restype = i32
+    L.hmc_set_bond_masks_async.argtypes = [vp, vp, i32]
+    L.hmc_plane_means_async.restype = i32
+    L.hmc_plane_means_async.argtypes = [vp, vp]
     _lib = L
     return L
 
@@ -263,6 +274,19 @@ class Lattice:
         m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(self.n))
         self._check(self._lib.hmc_set_bond_masks(self._h, m.ctypes.data))
 
+    def set_bond_masks_async(self, mask, check=True):
+        """Enqueue the bond masks from a pinned uint8 torch tensor of one byte
+        per site (kept alive by the lattice until replaced), without waiting."""
+        assert mask.dtype == torch.uint8 and not mask.is_cuda and mask.numel() == self.n
+        self._mask_host = mask
+        self._check(self._lib.hmc_set_bond_masks_async(self._h, ctypes.c_void_p(mask.data_ptr()), int(bool(check))))
+
+    def plane_means_async(self, dev_out):
+        """Enqueue the plane means into a device float64 tensor of nz x 3
+        (or 3 nz) elements, without waiting."""
+        assert dev_out.dtype == torch.float64 and dev_out.is_cuda and dev_out.numel() >= 3 * self.shape[2]
+        self._check(self._lib.hmc_plane_means_async(self._h, ctypes.c_void_p(dev_out.data_ptr())))
+
     def plane_means(self):
         """Mean spin of every z plane of the current spins, shape (nz, 3)."""
         out = np.empty((self.shape[2], 3), dtype=np.float64)
@@ -334,6 +358,43 @@ def measure_static(params, dev_spins, nbytes, stream=None, check=True):
     d = _obs_dict(o)
     d["status"] = st
     return d
+
+
+class Snapshot:
+    """An asynchronous read of the chain states of some lattices (one
+    stream): copies into a pinned host buffer are enqueued at construction,
+    followed by an event.  ready() polls the event without blocking;
+    observables() waits for it if needed and converts each record as
+    hmc_observables would (accumulators; no fresh measurement)."""
+
+    def __init__(self, lattices, stream=None):
+        L = lib()
+        self.lattices = list(lattices)
+        self.rec = int(L.hmc_snapshot_bytes())
+        self.meta = [(l.n, l.params.precision) for l in self.lattices]
+        self.host = torch.empty(max(1, len(self.lattices)) * self.rec, dtype=torch.uint8, pin_memory=True)
+        hs = (ctypes.c_void_p * max(1, len(self.lattices)))(*[l._h for l in self.lattices])
+        st = L.hmc_snapshot_enqueue(hs, len(self.lattices), ctypes.c_void_p(self.host.data_ptr()))
+        if st != OK:
+            raise HmcError(st, L.hmc_strerror(st).decode())
+        self.event = torch.cuda.Event()
+        self.event.record(stream if stream is not None else self.lattices[0].stream)
+
+    def ready(self):
+        return self.event.query()
+
+    def observables(self):
+        self.event.synchronize()
+        L = lib()
+        out = []
+        base = self.host.data_ptr()
+        for i, (n, prec) in enumerate(self.meta):
+            o = Obs()
+            st = L.hmc_snapshot_observables(ctypes.c_void_p(base + i * self.rec), n, prec, ctypes.byref(o))
+            d = _obs_dict(o)
+            d["status"] = st
+            out.append(d)
+        return out
 
 
 def _timing_dict(t):

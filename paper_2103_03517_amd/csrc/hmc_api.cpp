@@ -322,19 +322,15 @@ int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes, void* h
     memset(&L->init_state, 0, sizeof(L->init_state));
     L->init_state.theta = p->theta0_deg;
 
-    hipError_t e = hipMemcpyAsync(base + lay.off_c1, L->c1d, sizeof(L->c1d), hipMemcpyHostToDevice, L->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(base + lay.off_c1 + 181 * sizeof(double), L->c1f, sizeof(L->c1f), hipMemcpyHostToDevice,
-                           L->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d.st, &L->init_state, sizeof(DevState), hipMemcpyHostToDevice, L->stream);
+    // nothing is copied from host memory and nothing waits: the chain state
+    // and the cone table are written by a kernel from its arguments
+    hipError_t e = hmc::launch_setup(L->d, L->c1d, p->theta0_deg, base + lay.off_c1, L->stream);
     // every bond active until hmc_set_bond_masks says otherwise
     if (e == hipSuccess && d.mask) e = hipMemsetAsync(d.mask, 0x3F, 2 * (size_t)d.Nc, L->stream);
     if (e != hipSuccess) { delete L; return HMC_EHIP; }
     st = launch(L, 3, "init kernel", [&] { return hmc::launch_init(L->d, L->stream); });
     if (st == HMC_OK) st = measure(L);
-    if (st == HMC_OK) e = hipStreamSynchronize(L->stream);
-    if (st != HMC_OK || e != hipSuccess) { delete L; return st != HMC_OK ? st : HMC_EHIP; }
+    if (st != HMC_OK) { delete L; return st; }
     *out = L;
     return HMC_OK;
 }
@@ -495,50 +491,81 @@ int hmc_reset_stats(hmc_lattice* L)
     return HMC_OK;
 }
 
-int hmc_set_bond_masks(hmc_lattice* L, const uint8_t* host_mask)
+}  // extern "C"
+
+namespace {
+
+// A bond must be active or cut at both of its ends (bit k of a site and the
+// opposite bit of its neighbour k); bonds across an open z boundary do not
+// exist and are not checked.  Row by row, without divisions.
+int check_bond_masks(hmc_lattice* L, const uint8_t* host_mask)
 {
-    if (!L || !host_mask) return HMC_EINVAL;
     const DevLattice& d = L->d;
-    if (!d.mask) return fail(L, HMC_EINVAL, "the lattice was created without bond masks");
-    const int64_t nx = d.nx, ny = d.ny, nz = d.nz;
-    // a bond must be active or cut at both of its ends (bit k of a site and
-    // the opposite bit of its neighbour k); bonds across an open z boundary
-    // do not exist and are not checked
-    for (int64_t z = 0; z < nz; ++z)
-        for (int64_t y = 0; y < ny; ++y)
+    const int64_t nx = d.nx, ny = d.ny, nz = d.nz, plane = nx * ny;
+    for (int64_t z = 0; z < nz; ++z) {
+        const bool zcut = d.zbound == 2 && z == nz - 1;
+        const int64_t zn = z + 1 == nz ? 0 : z + 1;
+        for (int64_t y = 0; y < ny; ++y) {
+            const int64_t yn = y + 1 == ny ? 0 : y + 1;
+            const uint8_t* row = host_mask + nx * (y + ny * z);
+            const uint8_t* rowy = host_mask + nx * (yn + ny * z);
+            const uint8_t* rowz = host_mask + nx * y + plane * zn;
             for (int64_t x = 0; x < nx; ++x) {
-                const int64_t i = x + nx * (y + ny * z);
-                const uint8_t m = host_mask[i];
-                if (m & 0xC0u) return fail(L, HMC_EINVAL, "bond masks use bits 0..5 only");
-                const int64_t jx = ((x + 1) % nx) + nx * (y + ny * z);
-                const int64_t jy = x + nx * (((y + 1) % ny) + ny * z);
-                const int64_t jz = x + nx * (y + ny * ((z + 1) % nz));
-                const bool zcut = d.zbound == 2 && z == nz - 1;
-                if (((m >> 1) & 1u) != (host_mask[jx] & 1u) || ((m >> 3) & 1u) != ((host_mask[jy] >> 2) & 1u) ||
-                    (!zcut && ((m >> 5) & 1u) != ((host_mask[jz] >> 4) & 1u))) {
+                const uint8_t m = row[x];
+                const uint8_t mx = row[x + 1 == nx ? 0 : x + 1];
+                if ((m & 0xC0u) || ((m >> 1) & 1u) != (mx & 1u) || ((m >> 3) & 1u) != ((rowy[x] >> 2) & 1u) ||
+                    (!zcut && ((m >> 5) & 1u) != ((rowz[x] >> 4) & 1u))) {
                     char msg[160];
-                    snprintf(msg, sizeof(msg), "bond masks are not symmetric at site (%lld, %lld, %lld)",
-                             (long long)x, (long long)y, (long long)z);
+                    if (m & 0xC0u) snprintf(msg, sizeof(msg), "bond masks use bits 0..5 only");
+                    else
+                        snprintf(msg, sizeof(msg), "bond masks are not symmetric at site (%lld, %lld, %lld)",
+                                 (long long)x, (long long)y, (long long)z);
                     return fail(L, HMC_EINVAL, msg);
                 }
             }
-    std::vector<uint8_t> split;
-    try {
-        split.resize(2 * (size_t)d.Nc);
-    } catch (...) {
-        return fail(L, HMC_ENOMEM, "host staging buffer");
+        }
     }
-    // colour-split order: site i = 2k + p has colour c = (x + y + z) & 1
-    for (int64_t k = 0; k < d.Nc; ++k) {
-        const int64_t r = k / d.hx;
-        const int64_t y = r % d.ny, z = r / d.ny;
-        for (int c = 0; c < 2; ++c) split[(size_t)c * d.Nc + k] = host_mask[2 * k + ((y + z + c) & 1)];
-    }
-    hipError_t e = hipMemcpyAsync(d.mask, split.data(), split.size(), hipMemcpyHostToDevice, L->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    return HMC_OK;
+}
+
+// Copies the site-ordered masks into the workspace's constrained working
+// area (free between constrained calls; 16 bytes per site or more) and
+// splits them by colour on the device.
+int upload_bond_masks(hmc_lattice* L, const uint8_t* host_mask)
+{
+    uint8_t* tmp = static_cast<uint8_t*>(L->d.aos);
+    hipError_t e = hipMemcpyAsync(tmp, host_mask, (size_t)L->d.N, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = hmc::launch_split_masks(L->d, tmp, L->stream);
     if (e != hipSuccess) return fail(L, HMC_EHIP, "copying the bond masks", e);
     L->m_valid = false;
     return HMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hmc_set_bond_masks(hmc_lattice* L, const uint8_t* host_mask)
+{
+    if (!L || !host_mask) return HMC_EINVAL;
+    if (!L->d.mask) return fail(L, HMC_EINVAL, "the lattice was created without bond masks");
+    int st = check_bond_masks(L, host_mask);
+    if (st == HMC_OK) st = upload_bond_masks(L, host_mask);
+    if (st != HMC_OK) return st;
+    hipError_t e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return fail(L, HMC_EHIP, "copying the bond masks", e);
+    return HMC_OK;
+}
+
+int hmc_set_bond_masks_async(hmc_lattice* L, const uint8_t* host_mask, int32_t check)
+{
+    if (!L || !host_mask) return HMC_EINVAL;
+    if (!L->d.mask) return fail(L, HMC_EINVAL, "the lattice was created without bond masks");
+    if (check) {
+        int st = check_bond_masks(L, host_mask);
+        if (st != HMC_OK) return st;
+    }
+    return upload_bond_masks(L, host_mask);
 }
 
 int hmc_plane_means(hmc_lattice* L, double* host_out)
@@ -744,9 +771,44 @@ int hmc_read_timing(hmc_lattice* L, hmc_timing* out)
 void hmc_destroy(hmc_lattice* L)
 {
     if (!L) return;
-    (void)hipStreamSynchronize(L->stream);
+    // launches copy their arguments, so work still queued on the stream does
+    // not use the handle; only the timing events go with it
     L->timer.destroy();
     delete L;
+}
+
+size_t hmc_snapshot_bytes(void) { return sizeof(DevState); }
+
+int hmc_snapshot_enqueue(hmc_lattice* const* lattices, int32_t count, void* host_dst)
+{
+    if (!lattices || !host_dst || count < 0) return HMC_EINVAL;
+    for (int32_t i = 0; i < count; ++i)
+        if (!lattices[i] || lattices[i]->stream != lattices[0]->stream) return HMC_EINVAL;
+    char* out = static_cast<char*>(host_dst);
+    for (int32_t i = 0; i < count; ++i) {
+        hmc_lattice* L = lattices[i];
+        hipError_t e = hipMemcpyAsync(out + (size_t)i * sizeof(DevState), L->d.st, sizeof(DevState),
+                                      hipMemcpyDeviceToHost, L->stream);
+        if (e != hipSuccess) return fail(L, HMC_EHIP, "enqueueing a state snapshot", e);
+    }
+    return HMC_OK;
+}
+
+int hmc_snapshot_observables(const void* record, int64_t n, int32_t precision, hmc_obs* out)
+{
+    if (!record || !out || n <= 0 || (precision != 32 && precision != 64)) return HMC_EINVAL;
+    DevState s;
+    memcpy(&s, record, sizeof(s));
+    hmc_lattice shim;
+    shim.d.N = n;
+    shim.d.precision = precision;
+    return hmc::finish_observables(&shim, s, out);
+}
+
+int hmc_plane_means_async(hmc_lattice* L, double* dev_out)
+{
+    if (!L || !dev_out) return HMC_EINVAL;
+    return launch(L, 2, "plane-mean kernel", [&] { return hmc::launch_plane_means(L->d, dev_out, L->stream); });
 }
 
 const char* hmc_strerror(int status)

@@ -85,7 +85,14 @@ struct hmc_batch {
     };
     std::vector<Chunk> chunks;
     size_t chunk_bytes = 0;
-    // pinned staging of the uploads, reused once the previous copy is done
+    // pinned staging of the uploads: a ring of kRing buffers, each reused
+    // once the copy last made from it has run, so that the host can prepare
+    // uploads while earlier work is still queued; staging and upload_done
+    // name the buffer in use and its event
+    static constexpr int kRing = 4;
+    char* ring[kRing] = {};
+    hipEvent_t ring_ev[kRing] = {};
+    int ring_cur = 0;
     char* staging = nullptr;
     hipEvent_t upload_done = nullptr;
     bool table_valid = false;
@@ -128,8 +135,15 @@ void drop_graphs(hmc_batch* B)
     B->exec.assign(B->chunks.size(), {nullptr, nullptr});
 }
 
-// Waits until the staging buffer is free again (the previous upload ran).
-hipError_t staging_wait(hmc_batch* B) { return hipEventSynchronize(B->upload_done); }
+// Moves to the next staging buffer of the ring and waits until the upload
+// last made from it has run.
+hipError_t staging_wait(hmc_batch* B)
+{
+    B->ring_cur = (B->ring_cur + 1) % hmc_batch::kRing;
+    B->staging = B->ring[B->ring_cur];
+    B->upload_done = B->ring_ev[B->ring_cur];
+    return hipEventSynchronize(B->upload_done);
+}
 
 hipError_t upload(hmc_batch* B, size_t off, size_t bytes)
 {
@@ -319,8 +333,10 @@ void destroy_batch(hmc_batch* B)
     (void)hipStreamSynchronize(B->stream);
     drop_graphs(B);
     if (B->cap) (void)hipStreamDestroy(B->cap);
-    if (B->upload_done) (void)hipEventDestroy(B->upload_done);
-    if (B->staging) (void)hipHostFree(B->staging);
+    for (int r = 0; r < hmc_batch::kRing; ++r) {
+        if (B->ring_ev[r]) (void)hipEventDestroy(B->ring_ev[r]);
+        if (B->ring[r]) (void)hipHostFree(B->ring[r]);
+    }
     B->timer.destroy();
     delete B;
 }
@@ -379,14 +395,19 @@ int hmc_batch_create(hmc_lattice* const* lattices, int32_t count, void* dev_ws, 
     B->ws = static_cast<char*>(dev_ws);
     B->lay = lay;
     B->shape.assign(count, {0, 0});
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&B->staging), staging_bytes, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&B->upload_done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(B->upload_done, B->stream);
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < hmc_batch::kRing && e == hipSuccess; ++r) {
+        e = hipHostMalloc(reinterpret_cast<void**>(&B->ring[r]), staging_bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&B->ring_ev[r], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(B->ring_ev[r], B->stream);
+        if (e == hipSuccess) memset(B->ring[r], 0, staging_bytes);
+    }
     if (e != hipSuccess) {
         destroy_batch(B);
         return HMC_EHIP;
     }
-    memset(B->staging, 0, staging_bytes);
+    B->staging = B->ring[0];
+    B->upload_done = B->ring_ev[0];
     st = refresh_table(B);
     if (st == HMC_OK) {
         e = hipStreamSynchronize(B->stream);

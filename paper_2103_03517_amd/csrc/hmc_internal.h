@@ -89,6 +89,12 @@ inline bool pass_deep(const DevLattice& d)
 // Launchers (hmc_kernels.hip).  Each returns the HIP status of the launch;
 // *blocks receives the number of work-groups that wrote results.
 hipError_t launch_init(const DevLattice& d, hipStream_t s);
+// Zeroes the chain state (cone angle theta0) and writes the cone table, 181
+// doubles at c1_dev followed by the same 181 values as floats.
+hipError_t launch_setup(const DevLattice& d, const double* c1d_host, int theta0, void* c1_dev, hipStream_t s);
+// Splits N bytes of bond masks in site order at src (device) into the
+// colour-split mask array of the lattice.
+hipError_t launch_split_masks(const DevLattice& d, const uint8_t* src, hipStream_t s);
 hipError_t launch_pass(const DevLattice& d, int colour, bool obs, int spt, int zc, double T, hipStream_t s,
                        int64_t* blocks);
 // Steps of a constrained call: copy the spins into the AoS working copy, the

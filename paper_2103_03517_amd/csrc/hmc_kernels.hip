@@ -33,6 +33,43 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(DevState* st, const 
 }
 
 // ---------------------------------------------------------------------------
+// Set-up of a lattice's workspace: the chain state (zeroed, cone angle
+// theta0) and the cone table 1 - cos(theta), both precisions, from values
+// passed by argument (so nothing is copied from host memory).
+// ---------------------------------------------------------------------------
+struct C1Table {
+    double d[181];
+    float f[181];
+};
+
+__global__ __launch_bounds__(kThreads) void setup_kernel(DevState* st, int theta0, const C1Table tab, double* c1d,
+                                                         float* c1f)
+{
+    const uint32_t t = threadIdx.x;
+    if (t < 181) {
+        c1d[t] = tab.d[t];
+        c1f[t] = tab.f[t];
+    }
+    uint32_t* w = reinterpret_cast<uint32_t*>(st);
+    for (uint32_t i = t; i < sizeof(DevState) / 4; i += kThreads) w[i] = 0u;
+    __syncthreads();
+    if (t == 0) st->theta = theta0;
+}
+
+hipError_t launch_setup(const DevLattice& d, const double* c1d_host, int theta0, void* c1_dev, hipStream_t s)
+{
+    C1Table tab;
+    for (int i = 0; i < 181; ++i) {
+        tab.d[i] = c1d_host[i];
+        tab.f[i] = (float)c1d_host[i];
+    }
+    double* c1d = static_cast<double*>(c1_dev);
+    float* c1f = reinterpret_cast<float*>(c1d + 181);
+    setup_kernel<<<1, kThreads, 0, s>>>(d.st, theta0, tab, c1d, c1f);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Initial spins: along a direction, or uniform on the sphere from Philox
 // tag 4 (z = 2 u0 - 1, azimuth 2 pi u1).
 // ---------------------------------------------------------------------------
@@ -508,6 +545,26 @@ int64_t max_blocks_for(int32_t nx, int32_t ny, int32_t nz)
 int64_t pass_blocks(const DevLattice& d, int spt, int zc)
 {
     return (int64_t)cdiv((uint64_t)d.P, (uint64_t)kThreads * spt) * (int64_t)cdiv((uint64_t)d.nz, (uint64_t)zc);
+}
+
+// Colour-split bond masks from masks in site order: site i = 2k + p of row
+// (y, z) has colour c = (x + y + z) & 1 and colour index k.
+__global__ __launch_bounds__(kThreads) void split_masks_kernel(const uint8_t* src, uint8_t* dst, uint32_t Nc,
+                                                               uint32_t hx, uint32_t ny)
+{
+    const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
+    if (k >= Nc) return;
+    const uint32_t r = k / hx;
+    const uint32_t y = r % ny, z = r / ny;
+#pragma unroll
+    for (uint32_t c = 0; c < 2; ++c) dst[(size_t)c * Nc + k] = src[2 * (size_t)k + ((y + z + c) & 1u)];
+}
+
+hipError_t launch_split_masks(const DevLattice& d, const uint8_t* src, hipStream_t s)
+{
+    split_masks_kernel<<<cdiv((uint64_t)d.Nc, kThreads), kThreads, 0, s>>>(src, d.mask, (uint32_t)d.Nc,
+                                                                             (uint32_t)d.hx, (uint32_t)d.ny);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(const DevLattice& d, hipStream_t s)

@@ -104,6 +104,25 @@ def mt_sweep(temps, size=256, precision=32, equil=2000, samples=4000, block=200,
     return out
 
 
+def mt_gate(temps, size=256, equil=2000, samples=8000, block=200, init="aligned", seeds=(7, 8), Ku=0.005,
+            log=None):
+    """FP32 against FP64 along the increasing-temperature protocol: mt_sweep
+    at both precisions with independent Philox keys (seeds), and per
+    temperature |dm| of <|m|>, its z-score, the z-scores of <E>/N and chi_l,
+    the runs' stationarity z-scores (first against second half of each
+    window) and the gate of compare_precisions."""
+    r32 = mt_sweep(temps, size=size, precision=32, equil=equil, samples=samples, block=block, seed=seeds[0],
+                   init=init, Ku=Ku, log=log)
+    r64 = mt_sweep(temps, size=size, precision=64, equil=equil, samples=samples, block=block, seed=seeds[1],
+                   init=init, Ku=Ku, log=log)
+    for r in r32 + r64:
+        r["edge"] = size
+    rows = compare_precisions(r32, r64)
+    for c, a, b in zip(rows, r32, r64):
+        c.update(m32=a["m"][0], m64=b["m"][0], E32=a["E"], E64=b["E"], chi32=a["chi"][0], chi64=b["chi"][0])
+    return {"fp32": r32, "fp64": r64, "compare": rows}
+
+
 def block_stats_from_reads(reads, n, T):
     """Block statistics from cumulative observables read at the end of each
     block: block sums are differences of the running sums (n mean, n (var +
@@ -385,6 +404,25 @@ def eq4_vs_constrained(temps=(0.2, 0.4, 0.6, 0.8, 1.0, 1.2, 1.4), size=128, prec
     return res
 
 
+def eq4_convergence(Kcs=(0.05, 0.02, 0.01), temps=(0.4, 0.8), size=64, thetas=tuple(range(0, 91, 15)),
+                    sweeps=3000, equil=1000, log=None):
+    """Eq. 4 against the torque route as the anisotropy shrinks: for each Kc,
+    k_eq4 - k_torque at each temperature with its combined error.  The two
+    routes agree to first order in Kc/J (Callen-Callen theory), so the
+    difference should shrink in proportion to Kc."""
+    out = []
+    for Kc in Kcs:
+        r = eq4_vs_constrained(temps=temps, size=size, Kc=Kc, thetas=thetas, sweeps=sweeps, equil=equil)
+        for row in r["rows"]:
+            se = math.hypot(row["se_k_torque"], row["se_k_eq4"])
+            out.append({"Kc": Kc, "T": row["T"], "m": row["m"], "k_torque": row["k_torque"],
+                        "k_eq4": row["k_eq4"], "diff": row["k_eq4"] - row["k_torque"], "se_diff": se})
+            if log:
+                log(f"Kc={Kc} T={row['T']}: k_torque {row['k_torque']:.5f} k_eq4 {row['k_eq4']:.5f} "
+                    f"diff {row['k_eq4'] - row['k_torque']:+.5f} +- {se:.5f}")
+    return out
+
+
 def uniaxial_K(temps, size=64, precision=32, thetas=(0, 15, 30, 45, 60, 75, 90), Ku=0.01, J=1.0, sweeps=3000,
                equil=1000, seed=8):
     """K(T) of a uniaxial term along z from constrained runs at a few angles
@@ -578,6 +616,15 @@ def main(argv=None):
     e4.add_argument("--size", type=int, default=128)
     e4.add_argument("--sweeps", type=int, default=3000)
     e4.add_argument("--equil", type=int, default=1000)
+    mg = sub.add_parser("mtgate", help="FP32 against FP64 along the increasing-temperature protocol")
+    mg.add_argument("--size", type=int, default=256)
+    mg.add_argument("--equil", type=int, default=2000)
+    mg.add_argument("--samples", type=int, default=8000)
+    mg.add_argument("--block", type=int, default=200)
+    ec = sub.add_parser("eq4conv", help="Eq. 4 minus the torque route as Kc shrinks")
+    ec.add_argument("--Kc", type=float, nargs="+", default=[0.05, 0.02, 0.01])
+    ec.add_argument("--temps", type=float, nargs="+", default=[0.4, 0.8])
+    ec.add_argument("--size", type=int, default=64)
     fg = sub.add_parser("films", help="granular films over thickness and grain size (mean Tc table)")
     fg.add_argument("--n", type=int, default=1024)
     fg.add_argument("--nz", type=int, nargs="+", default=[5, 10, 15])
@@ -608,6 +655,11 @@ def main(argv=None):
         res = film_grid(n=args.n, thicknesses=args.nz, diameters=args.diameters, log=log)
     elif args.cmd == "eq4":
         res = eq4_vs_constrained(size=args.size, sweeps=args.sweeps, equil=args.equil, log=log)
+    elif args.cmd == "mtgate":
+        temps = np.round(np.linspace(0.1, 1.6, 16), 3).tolist()
+        res = mt_gate(temps, size=args.size, equil=args.equil, samples=args.samples, block=args.block, log=log)
+    elif args.cmd == "eq4conv":
+        res = eq4_convergence(Kcs=args.Kc, temps=args.temps, size=args.size, log=log)
     elif args.cmd == "anisotropy":
         res = anisotropy_run(size=args.size, sweeps=args.sweeps, equil=args.equil, log=log)
     elif args.cmd == "batched":

@@ -1,15 +1,30 @@
-"""Continuous batching of m(T) and domain-wall jobs on one device.
+"""Continuous batching of mixed jobs on one device.
 
 Requests (one lattice, one temperature, a sweep budget each) arrive over
-time.  An m(T) job runs a periodic cube and reports <|m|>, chi and E with
-batch-means errors; a wall job runs a lattice that is anti-periodic along z
-from a sharp wall and reports the fitted wall width (Sec. 3, Eq. 5).  The loop admits waiting requests in arrival order whenever a slot is
-free and their workspace fits in the HBM budget, advances every admitted job
-together through the batch interface (one launch per colour pass for all of
-them, each job with its own temperature and its own sample flag), reads the
-observables at the jobs' block ends, and retires finished jobs, releasing
-their memory for the next admissions.  Jobs that arrive while others run join
-the batch at the next tick, so their work overlaps on the device.
+time.  Four kinds of job, after the paper's uses of the method:
+
+* "mt": m(T) of a periodic cube started along z (Sec. 3), reporting <|m|>,
+  chi and E with batch-means errors;
+* "wall": a lattice anti-periodic along z started from the T = 0 wall
+  profile, reporting the fitted wall width (Sec. 3, Eq. 5);
+* "aniso": a constrained run (Table A2) of a periodic cube with cubic
+  anisotropy, the moment held along e_C(theta, phi), reporting the mean
+  torque, its component -<tau>.e_phi and the anisotropy energy (Sec. 3);
+* "film": a granular film, open along z with Voronoi grains whose
+  intergrain exchange is cut (Sec. 4), reporting m(T).
+
+The loop admits waiting requests in arrival order whenever a slot is free and
+their workspace fits in the HBM budget.  m(T) and wall jobs advance together
+through the batch interface (one launch per colour pass for all of them,
+each with its own temperature and sample flag); constrained and film jobs,
+which the batch kernels do not cover, are swept one by one on the same
+stream in the same tick.  The host never waits for a read: at a job's block
+end it enqueues an asynchronous snapshot of the chain states (and, for a
+wall, of its plane profile) followed by an event, and consumes the snapshot
+when the event has passed; it runs at most a few ticks ahead of the device,
+waiting on the oldest tick's event only when it gets further ahead.  A job
+finishes when its last snapshot has reached the host; it is then retired and
+its memory released for the next admissions.
 
 A job's chain depends only on its own key (seed, instance), its temperature,
 its sweep schedule and its launch shape, so its result is the same alone and
@@ -20,29 +35,38 @@ in any mix (tests check this bit for bit).
 import argparse
 import collections
 import json
+import math
 import sys
 import time
 
 import numpy as np
 import torch
 
-from . import Batch, Lattice, workspace_bytes, make_params
-from .protocols import block_stats_from_reads
+from . import Batch, Lattice, Snapshot, workspace_bytes, make_params
+from .protocols import block_stats_from_reads, ec_of, blocking_se
+from . import films as F
 from . import walls as W
+
+KINDS = ("mt", "wall", "aniso", "film")
 
 
 class Job:
     """One request: `equil` unsampled sweeps, then `samples` sampled sweeps
     read every `block` sweeps.  kind "mt": an edge^3 periodic cube started
-    along z; kind "wall": a shape = (nx, ny, nz) lattice anti-periodic along
-    z, started from a sharp wall, whose m_z plane profile is kept at every
-    block end and fitted when the job retires."""
+    along z; "wall": a shape = (nx, ny, nz) lattice anti-periodic along z,
+    started from the T = 0 wall, whose m_z plane profile is kept at every
+    block end and fitted when the job retires; "aniso": an edge^3 periodic
+    cube with cubic anisotropy Kc, started and held along e_C(theta, phi)
+    (constrained sweeps); "film": a shape = (nx, ny, nz) film open along z
+    with Voronoi grains of mean diameter `diameter` (grain seed `grain_seed`),
+    started along z."""
 
     def __init__(self, edge, T, equil=200, samples=800, block=100, seed=5, instance=0, Ku=0.01,
-                 J=1.0, arrival=0.0, name=None, kind="mt", shape=None):
+                 J=1.0, arrival=0.0, name=None, kind="mt", shape=None, Kc=0.0, theta=0.0, phi=0.0,
+                 diameter=16.0, grain_seed=9):
         if samples % block or equil < 0 or samples <= 0 or block <= 0:
             raise ValueError("samples must be a positive multiple of block")
-        if kind not in ("mt", "wall"):
+        if kind not in KINDS:
             raise ValueError(f"unknown job kind {kind}")
         self.kind = kind
         self.shape = tuple(int(v) for v in shape) if shape is not None else (int(edge),) * 3
@@ -51,11 +75,16 @@ class Job:
         self.edge, self.T = int(edge), float(T)
         self.equil, self.samples, self.block = int(equil), int(samples), int(block)
         self.seed, self.instance, self.Ku, self.J = int(seed), int(instance), float(Ku), float(J)
+        self.Kc, self.theta, self.phi = float(Kc), float(theta), float(phi)
+        self.diameter, self.grain_seed = float(diameter), int(grain_seed)
         self.arrival = float(arrival)
         self.name = name if name is not None else f"job{instance}"
         self.done = 0
         self.reads = []
+        self.expected_reads = self.samples // self.block
         self.lattice = None
+        self.prof_dev = None
+        self.prof_enqueued = 0
         self.admitted = self.finished = None
         self.result = None
 
@@ -63,10 +92,29 @@ class Job:
     def total(self):
         return self.equil + self.samples
 
+    @property
+    def batched(self):
+        """m(T) and wall jobs run in the batch; constrained and film jobs alone."""
+        return self.kind in ("mt", "wall")
+
+    def e_c(self):
+        return ec_of(self.theta, self.phi)
+
+    def lattice_kw(self, precision):
+        kw = dict(precision=precision, J=self.J, seed=self.seed, instance=self.instance)
+        if self.kind == "aniso":
+            kw.update(Kc=self.Kc, Ku=0.0, init="aligned", init_dir=self.e_c())
+        elif self.kind == "film":
+            kw.update(Ku=self.Ku, eu=(0.0, 0.0, 1.0), init="aligned", boundary_z="open", bond_masks=True)
+        elif self.kind == "wall":
+            kw.update(Ku=self.Ku, eu=(0.0, 0.0, 1.0), init="wall", init_width=W.zero_temperature_width(self.J, self.Ku),
+                      boundary_z="antiperiodic")
+        else:
+            kw.update(Ku=self.Ku, eu=(0.0, 0.0, 1.0), init="aligned")
+        return kw
+
     def params(self, precision):
-        return make_params(*self.shape, precision=precision, J=self.J, Ku=self.Ku, eu=(0.0, 0.0, 1.0),
-                           seed=self.seed, instance=self.instance, init="aligned",
-                           boundary_z="antiperiodic" if self.kind == "wall" else "periodic")
+        return make_params(*self.shape, **self.lattice_kw(precision))
 
     def sampling(self):
         return self.done >= self.equil
@@ -81,25 +129,49 @@ class Job:
 
 def poisson_jobs(rate=20.0, seconds=10.0, seed=5, edges=(32, 48, 64, 96, 128, 160, 192),
                  t_lo=0.05, t_hi=1.7, wall_fraction=0.0, wall_shape=(64, 64, 512), wall_t_hi=1.2,
-                 wall_sweeps=(1000, 1000, 100), **job_kw):
-    """Poisson arrivals: exponential gaps of mean 1/rate.  With probability
-    wall_fraction a job is a wall job on wall_shape at T ~ U(t_lo,
-    wall_t_hi) with (equil, samples, block) = wall_sweeps; otherwise an m(T)
-    job with the edge uniform over `edges` and T ~ U(t_lo, t_hi)."""
+                 wall_sweeps=(1000, 1000, 100), aniso_fraction=0.0, aniso_edges=(32, 48, 64), aniso_Kc=0.05,
+                 aniso_t=(0.2, 1.4), aniso_sweeps=(500, 500, 100), film_fraction=0.0, film_n=1024,
+                 film_nz=(5, 10, 15), film_diameters=(8.0, 16.0, 24.0), film_t_hi=1.4, film_sweeps=(200, 800, 100),
+                 **job_kw):
+    """Poisson arrivals: exponential gaps of mean 1/rate.  Each job is a wall
+    job with probability wall_fraction (wall_shape, T ~ U(t_lo, wall_t_hi)),
+    a constrained anisotropy job with probability aniso_fraction (edge from
+    aniso_edges, Kc = aniso_Kc, theta uniform in 0..90 degrees by 10, phi 0 or
+    45, T ~ U(aniso_t)), a film job with probability film_fraction
+    (film_n^2 x nz, nz from film_nz, grain diameter from film_diameters, T ~
+    U(t_lo, film_t_hi)), else an m(T) job with the edge uniform over `edges`
+    and T ~ U(t_lo, t_hi).  (equil, samples, block) per kind as given."""
     rng = np.random.default_rng(seed)
     jobs, t, i = [], 0.0, 0
+    base = {k: v for k, v in job_kw.items() if k not in ("equil", "samples", "block")}
     while True:
         t += rng.exponential(1.0 / rate)
         if t >= seconds:
             break
         edge = int(rng.choice(edges))
         T = float(rng.uniform(t_lo, t_hi))
-        if rng.uniform() < wall_fraction:
+        u = rng.uniform()
+        if u < wall_fraction:
             eq, smp, blk = wall_sweeps
             T = t_lo + (T - t_lo) * (wall_t_hi - t_lo) / (t_hi - t_lo)
             jobs.append(Job(edge, T, equil=eq, samples=smp, block=blk, seed=seed, instance=i, arrival=t,
-                            kind="wall", shape=wall_shape,
-                            **{k: v for k, v in job_kw.items() if k not in ("equil", "samples", "block")}))
+                            kind="wall", shape=wall_shape, **base))
+        elif u < wall_fraction + aniso_fraction:
+            eq, smp, blk = aniso_sweeps
+            e = int(rng.choice(aniso_edges))
+            th = 10.0 * int(rng.integers(0, 10))
+            ph = 45.0 * int(rng.integers(0, 2))
+            Ta = float(rng.uniform(*aniso_t))
+            jobs.append(Job(e, Ta, equil=eq, samples=smp, block=blk, seed=seed, instance=i, arrival=t,
+                            kind="aniso", Kc=aniso_Kc, theta=th, phi=ph,
+                            **{k: v for k, v in base.items() if k not in ("Ku",)}))
+        elif u < wall_fraction + aniso_fraction + film_fraction:
+            eq, smp, blk = film_sweeps
+            nz = int(rng.choice(film_nz))
+            d = float(rng.choice(film_diameters))
+            Tf = t_lo + (T - t_lo) * (film_t_hi - t_lo) / (t_hi - t_lo)
+            jobs.append(Job(film_n, Tf, equil=eq, samples=smp, block=blk, seed=seed, instance=i, arrival=t,
+                            kind="film", shape=(film_n, film_n, nz), diameter=d, **base))
         else:
             jobs.append(Job(edge, T, seed=seed, instance=i, arrival=t, **job_kw))
         i += 1
@@ -107,23 +179,27 @@ def poisson_jobs(rate=20.0, seconds=10.0, seed=5, edges=(32, 48, 64, 96, 128, 16
 
 
 class Server:
-    """The continuous-batching loop.  `shapes` maps an edge to the launch
-    shape (sites per thread, z chunk) its lattices use; `quantum` is the
-    largest number of sweeps enqueued per tick."""
+    """The continuous-batching loop.  `shapes` maps a lattice shape to the
+    launch shape (sites per thread, z chunk) its lattices use; `quantum` is
+    the largest number of sweeps enqueued per tick; the host runs at most
+    `ahead` ticks ahead of the device."""
 
     def __init__(self, precision=32, hbm_budget=32 << 30, max_slots=64, quantum=50, shapes=None,
-                 graph=0, log=None):
+                 graph=0, ahead=3, log=None):
         self.precision = int(precision)
         self.hbm_budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.quantum = int(quantum)
         self.shapes = dict(shapes or {})
         self.graph = int(graph)
+        self.ahead = int(ahead)
         self.log = log
-        self.stats = {"ticks": 0, "rebuilds": 0, "max_active": 0, "max_bytes": 0, "sweep_launches": 0}
-        # host seconds per phase of the loop (the device waits during admit,
-        # rebuild and retire, which follow a synchronising read)
-        self.phase_s = {"admit": 0.0, "rebuild": 0.0, "enqueue": 0.0, "read": 0.0, "retire": 0.0}
+        self._grains = {}
+        self.stats = {"ticks": 0, "rebuilds": 0, "max_active": 0, "max_bytes": 0, "sweep_launches": 0,
+                      "snapshots": 0}
+        # host seconds per phase of the loop; "wait" is the time spent
+        # blocked on the device when the host got `ahead` ticks ahead
+        self.phase_s = {"admit": 0.0, "rebuild": 0.0, "enqueue": 0.0, "read": 0.0, "retire": 0.0, "wait": 0.0}
 
     def need_bytes(self, job):
         return workspace_bytes(job.params(self.precision))
@@ -141,24 +217,35 @@ class Server:
         self.shapes.update({s: tuple(ln) for s, ln in zip(shapes, launch)})
         return dict(self.shapes)
 
+    def _film_masks(self, job):
+        """Bond masks of a film as a pinned tensor, built once per film
+        configuration (the grain map does not change with the thickness);
+        returns (masks, first use)."""
+        key = (job.shape, job.diameter, job.grain_seed)
+        first = key not in self._grains
+        if first:
+            g, _ = F.voronoi_grains(job.shape[0], job.shape[1], job.diameter, job.grain_seed)
+            m = torch.from_numpy(F.grain_bond_masks(g, job.shape[2])).pin_memory()
+            self._grains[key] = m
+        return self._grains[key], first
+
     def _admit(self, job, now):
+        job.lattice = Lattice(*job.shape, **job.lattice_kw(self.precision))
+        if job.kind == "film":
+            # enqueued without waiting; checked on the host the first time
+            masks, first = self._film_masks(job)
+            job.lattice.set_bond_masks_async(masks, check=first)
         if job.kind == "wall":
-            # the T = 0 wall profile, written on the device
-            job.lattice = Lattice(*job.shape, precision=self.precision, J=job.J, Ku=job.Ku, eu=(0.0, 0.0, 1.0),
-                                  seed=job.seed, instance=job.instance, init="wall",
-                                  init_width=W.zero_temperature_width(job.J, job.Ku), boundary_z="antiperiodic")
-        else:
-            job.lattice = Lattice(*job.shape, precision=self.precision, J=job.J, Ku=job.Ku, eu=(0.0, 0.0, 1.0),
-                                  seed=job.seed, instance=job.instance, init="aligned")
-        if job.shape in self.shapes:
+            job.prof_dev = torch.empty((job.expected_reads, job.shape[2], 3), dtype=torch.float64, device="cuda")
+        if job.shape in self.shapes and job.kind != "film":
             job.lattice.set_launch(*self.shapes[job.shape])
         job.admitted = now
         job.bytes = self.need_bytes(job)
 
     @staticmethod
-    def _fit_walls(job):
+    def _fit_walls(job, profiles):
         fits = []
-        for prof in job.profiles:
+        for prof in profiles:
             try:
                 fits.append(W.fit_wall(prof, delta_guess=W.zero_temperature_width(job.J, job.Ku)))
             except RuntimeError:
@@ -167,21 +254,32 @@ class Server:
             f = np.array(fits)
             job.result.update(delta=float(f[:, 2].mean()), m_wall=float(f[:, 0].mean()), wall_fits=len(f))
 
-    def _retire(self, job, now, pool, clock):
-        job.result = block_stats_from_reads(job.reads, job.lattice.n, job.T)
+    @staticmethod
+    def _aniso_result(job):
+        """Mean torque, its component -<tau>.e_phi with its blocking error,
+        and the anisotropy energy, from the cumulative constrained samples."""
+        ephi = np.array([-math.sin(math.radians(job.phi)), math.cos(math.radians(job.phi)), 0.0])
+        g, prev = [], (0, np.zeros(3))
+        for r in job.reads:
+            ns = r["torque_samples"]
+            tsum = ns * np.asarray(r["mean_torque"])
+            g.append(-float((tsum - prev[1]) @ ephi) / (ns - prev[0]))
+            prev = (ns, tsum)
+        last = job.reads[-1]
+        return {"theta": job.theta, "phi": job.phi, "torque": last["mean_torque"], "g": float(np.mean(g)),
+                "se_g": float(blocking_se(np.array(g)[:, None])[0]), "E_anis": last["mean_Eanis"]}
+
+    def _retire(self, job, now):
+        job.result = block_stats_from_reads(job.reads, job.n, job.T)
         job.result.update(edge=job.edge, shape=list(job.shape), kind=job.kind,
                           sweeps=job.reads[-1]["sweeps_done"], theta_deg=job.reads[-1]["theta_deg"])
+        if job.kind == "aniso":
+            job.result.update(self._aniso_result(job))
+        if job.kind == "film":
+            job.result.update(diameter=job.diameter)
         job.lattice.close()
         job.lattice = None
-        if job.kind == "wall":
-            # the profile fits run beside the loop (the main thread mostly
-            # waits on the device); the job finishes when its fits are done
-            def work(j=job):
-                self._fit_walls(j)
-                j.finished = clock()
-            return pool.submit(work)
         job.finished = now
-        return None
 
     def run(self, jobs, realtime=True):
         """Serves `jobs` (arrival times in seconds from the start).  With
@@ -193,7 +291,10 @@ class Server:
             if self.need_bytes(j) > self.hbm_budget:
                 raise ValueError(f"{j.name} needs {self.need_bytes(j)} bytes, above the HBM budget")
         waiting = collections.deque()
-        active = []
+        active = []          # admitted, still sweeping
+        draining = []        # all sweeps enqueued, reads still in flight
+        inflight = collections.deque()   # (Snapshot, jobs, wall profile copies)
+        ticks = collections.deque()      # events of the ticks the device may still be running
         used = 0
         batch = None
         changed = True
@@ -205,80 +306,123 @@ class Server:
         def clock():
             return time.perf_counter() - t0
 
-        from concurrent.futures import ThreadPoolExecutor
-        pool = ThreadPoolExecutor(max_workers=2)
-        futures = []
         done = []
-        while pending or waiting or active:
+        stream = torch.cuda.current_stream()
+
+        def consume(block):
+            """Takes every snapshot that has reached the host (all of them,
+            waiting if needed, when block) and retires the jobs whose last
+            read it was."""
+            nonlocal used
+            t_ph = time.perf_counter()
+            while inflight and (block or inflight[0][0].ready()):
+                snap, js, walls = inflight.popleft()
+                obs = snap.observables()
+                for j, o in zip(js, obs):
+                    j.reads.append(o)
+                for j, prof in walls:
+                    j.profiles.append(prof)
+                now = clock()
+                for j in js:
+                    if len(j.reads) == j.expected_reads:
+                        self._retire(j, now)
+                        if j.kind == "wall":
+                            self._fit_walls(j, j.profiles)
+                        used -= j.bytes
+                        done.append(j)
+                        draining.remove(j)
+            self.phase_s["read"] += time.perf_counter() - t_ph
+
+        while pending or waiting or active or draining or inflight:
             now = clock()
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
             t_ph = time.perf_counter()
-            while waiting and len(active) < self.max_slots and used + self.need_bytes(waiting[0]) <= self.hbm_budget:
+            while (waiting and len(active) + len(draining) < self.max_slots
+                   and used + self.need_bytes(waiting[0]) <= self.hbm_budget):
                 j = waiting.popleft()
                 self._admit(j, clock())
                 used += j.bytes
                 active.append(j)
-                changed = True
+                if j.batched:
+                    changed = True
             self.phase_s["admit"] += time.perf_counter() - t_ph
-            self.stats["max_active"] = max(self.stats["max_active"], len(active))
+            self.stats["max_active"] = max(self.stats["max_active"], len(active) + len(draining))
             self.stats["max_bytes"] = max(self.stats["max_bytes"], used)
             if not active:
-                if pending:
+                if inflight:
+                    consume(block=True)
+                elif pending:
                     time.sleep(max(0.0, pending[0].arrival - clock()))
                 continue
+            batched = [j for j in active if j.batched]
+            solo = [j for j in active if not j.batched]
             if changed:
                 t_ph = time.perf_counter()
-                if batch is None:
-                    # one batch for the whole run, sized for max_slots lattices
-                    batch = Batch([j.lattice for j in active], capacity=self.max_slots)
-                    if self.graph:
-                        batch.set_graph(self.graph)
-                else:
-                    batch.set_lattices([j.lattice for j in active])
-                self.stats["rebuilds"] += 1
+                if batched:
+                    if batch is None:
+                        # one batch for the whole run, sized for max_slots lattices
+                        batch = Batch([j.lattice for j in batched], capacity=self.max_slots)
+                        if self.graph:
+                            batch.set_graph(self.graph)
+                    else:
+                        batch.set_lattices([j.lattice for j in batched])
+                    self.stats["rebuilds"] += 1
                 changed = False
                 self.phase_s["rebuild"] += time.perf_counter() - t_ph
             q = min(self.quantum, min(j.next_event() for j in active))
             t_ph = time.perf_counter()
-            batch.sweep_each([j.T for j in active], [j.sampling() for j in active], q)
-            self.phase_s["enqueue"] += time.perf_counter() - t_ph
+            if batched:
+                batch.sweep_each([j.T for j in batched], [j.sampling() for j in batched], q)
+            for j in solo:
+                if j.kind == "aniso":
+                    j.lattice.constrained_sweep(j.T, j.e_c(), q, sample=j.sampling())
+                else:
+                    j.lattice.sweep(j.T, q, sample=j.sampling())
             self.stats["ticks"] += 1
             self.stats["sweep_launches"] += q
             for j in active:
                 j.done += q
-            at_block_end = [j.sampling() and j.done > j.equil and (j.done - j.equil) % j.block == 0
-                            for j in active]
-            t_ph = time.perf_counter()
-            if any(at_block_end):
-                obs = batch.observables()
-                for j, o, hit in zip(active, obs, at_block_end):
-                    if hit:
-                        j.reads.append(o)
-                        if j.kind == "wall":
-                            j.profiles.append(j.lattice.plane_means()[:, 2])
-            self.phase_s["read"] += time.perf_counter() - t_ph
+            hit = [j for j in active if j.sampling() and j.done > j.equil and (j.done - j.equil) % j.block == 0]
+            if hit:
+                # the wall profiles (plane means into the job's device rows,
+                # m_z copied to pinned host memory), then the snapshot of
+                # every job at a block end, then one event behind them all
+                copies = []
+                for j in hit:
+                    if j.kind == "wall":
+                        row = j.prof_dev[j.prof_enqueued]
+                        j.lattice.plane_means_async(row)
+                        host = torch.empty(j.shape[2], dtype=torch.float64, pin_memory=True)
+                        host.copy_(row[:, 2], non_blocking=True)
+                        copies.append((j, host))
+                        j.prof_enqueued += 1
+                snap = Snapshot([j.lattice for j in hit], stream)
+                snap.event.record(stream)
+                inflight.append((snap, hit, [(j, h.numpy()) for j, h in copies]))
+                self.stats["snapshots"] += 1
+            self.phase_s["enqueue"] += time.perf_counter() - t_ph
+            # jobs whose sweeps are all enqueued leave the batch; they finish
+            # when their last snapshot arrives
             finished = [j for j in active if j.done >= j.total]
-            t_ph = time.perf_counter()
             if finished:
-                now = clock()
-                for j in finished:
-                    f = self._retire(j, now, pool, clock)
-                    if f is not None:
-                        futures.append(f)
-                    used -= j.bytes
-                    done.append(j)
                 active = [j for j in active if j.done < j.total]
-                changed = True
-                if self.log:
-                    self.log(f"t={now:.3f}s retired {len(finished)}, active {len(active)}, "
-                             f"waiting {len(waiting)}, pending {len(pending)}")
-            self.phase_s["retire"] += time.perf_counter() - t_ph
+                draining.extend(finished)
+                if any(j.batched for j in finished):
+                    changed = True
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            ticks.append(ev)
+            t_ph = time.perf_counter()
+            while len(ticks) > self.ahead:
+                ticks.popleft().synchronize()
+            self.phase_s["wait"] += time.perf_counter() - t_ph
+            consume(block=False)
+            if finished and self.log:
+                self.log(f"t={clock():.3f}s draining {len(draining)}, active {len(active)}, "
+                         f"waiting {len(waiting)}, pending {len(pending)}")
         if batch is not None:
             batch.close()
-        for f in futures:
-            f.result()
-        pool.shutdown()
         torch.cuda.synchronize()
         return done
 
@@ -287,9 +431,15 @@ def latency_summary(done, window=None):
     lat = np.array([j.finished - j.arrival for j in done])
     span = window if window is not None else max(j.finished for j in done)
     updates = sum(j.n * j.total for j in done)
-    return {"jobs": len(done), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "mean_s": float(lat.mean()), "max_s": float(lat.max()), "span_s": float(span),
-            "jobs_per_s": len(done) / span, "updates_per_s": updates / span}
+    out = {"jobs": len(done), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+           "mean_s": float(lat.mean()), "max_s": float(lat.max()), "span_s": float(span),
+           "jobs_per_s": len(done) / span, "updates_per_s": updates / span, "by_kind": {}}
+    for k in KINDS:
+        lk = np.array([j.finished - j.arrival for j in done if j.kind == k])
+        if len(lk):
+            out["by_kind"][k] = {"jobs": int(len(lk)), "p50_s": float(np.percentile(lk, 50)),
+                                 "p99_s": float(np.percentile(lk, 99))}
+    return out
 
 
 def main(argv=None):
@@ -305,11 +455,11 @@ def main(argv=None):
     def log(s):
         print(s, file=sys.stderr, flush=True)
 
-    jobs = poisson_jobs(args.rate, args.seconds)
+    jobs = poisson_jobs(args.rate, args.seconds, wall_fraction=0.15, aniso_fraction=0.15, film_fraction=0.1)
     srv = Server(precision=args.precision, hbm_budget=int(args.budget_gib * (1 << 30)), quantum=args.quantum,
                  log=log)
     if not args.no_tune:
-        log(f"tuned shapes: {srv.tune_shapes(sorted({j.shape for j in jobs}))}")
+        log(f"tuned shapes: {srv.tune_shapes(sorted({j.shape for j in jobs if j.batched}))}")
     done = srv.run(jobs)
     out = latency_summary(done)
     out.update(offered_jobs=len(jobs), rate=args.rate, stats=srv.stats)

@@ -104,6 +104,28 @@ def test_null_handles(hmc):
     assert L.hmc_state_bytes(None) == 0
     L.hmc_destroy(None)
     assert L.hmc_last_error(None) == b"no lattice"
+    assert L.hmc_plane_means_async(None, None) == -1
+
+
+def test_snapshot_host_checks(hmc):
+    """Snapshot records: a fixed size, argument checks before any device
+    work, and the host-side conversion of a cleared record."""
+    import ctypes
+    L = hmc.lib()
+    nb = L.hmc_snapshot_bytes()
+    assert 256 <= nb <= 1024 and nb % 8 == 0
+    assert L.hmc_snapshot_enqueue(None, 1, None) == -1
+    hs = (ctypes.c_void_p * 1)(None)
+    buf = ctypes.create_string_buffer(nb)
+    assert L.hmc_snapshot_enqueue(hs, 1, buf) == -1
+    assert L.hmc_snapshot_enqueue(hs, -1, buf) == -1
+    o = hmc.Obs()
+    assert L.hmc_snapshot_observables(None, 8, 32, ctypes.byref(o)) == -1
+    assert L.hmc_snapshot_observables(buf, 0, 32, ctypes.byref(o)) == -1
+    assert L.hmc_snapshot_observables(buf, 8, 16, ctypes.byref(o)) == -1
+    # an all-zero record: no samples, nothing accumulated, finite
+    assert L.hmc_snapshot_observables(buf, 8, 64, ctypes.byref(o)) == 0
+    assert o.n == 8 and o.samples == 0 and o.mean_E == 0.0 and o.precision == 64
 
 
 def test_batch_host_checks(hmc):

@@ -7,6 +7,7 @@ complete with latencies recorded.
 """
 import sys
 
+import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -32,14 +33,17 @@ def _mix(S, seed=5):
             S.Job(16, 1.6, instance=3, arrival=0.03, **kw),
             S.Job(24, 0.2, instance=4, arrival=0.05, **dict(kw, equil=20, samples=200)),
             S.Job(0, 0.3, instance=5, arrival=0.01, kind="wall", shape=(8, 8, 64), Ku=0.05, seed=seed,
-                  equil=100, samples=160, block=40)]
+                  equil=100, samples=160, block=40),
+            S.Job(12, 0.6, instance=6, arrival=0.01, kind="aniso", Kc=0.05, theta=30.0, phi=45.0, **kw),
+            S.Job(0, 0.8, instance=7, arrival=0.02, kind="film", shape=(24, 16, 3), diameter=5.0, **kw)]
 
 
 @pytest.mark.parametrize("precision", [32, 64])
 def test_result_same_alone_and_in_mix(S, precision):
     shapes = {(16,) * 3: (1, 4), (24,) * 3: (2, 8), (32,) * 3: (1, 16)}
     mixed = S.Server(precision=precision, quantum=30, shapes=shapes).run(_mix(S))
-    assert len(mixed) == 6
+    assert len(mixed) == 8
+    assert {j.kind for j in mixed} == {"mt", "wall", "aniso", "film"}
     for j in mixed:
         alone_job = [x for x in _mix(S) if x.instance == j.instance][0]
         alone = S.Server(precision=precision, quantum=7, shapes=shapes).run([alone_job])[0]
@@ -90,3 +94,48 @@ def test_wall_job_width_at_low_temperature(S):
     assert r["wall_fits"] == 10
     assert abs(r["delta"] / d0 - 1) < 0.06
     assert r["m_wall"] > 0.95
+
+
+def test_fp64_served_jobs_match_reference(S):
+    """FP64 jobs of three kinds served together (an m(T) job in the batch, a
+    constrained anisotropy job and a granular film swept alone) end where the
+    CPU reference ends after the same sweep schedule: the accumulators of the
+    last snapshot equal the reference's averages."""
+    from oracle import oracle as O
+    from paper_2103_03517_amd import films as F
+    kw = dict(equil=30, samples=60, block=20, seed=13)
+    jobs = [S.Job(8, 0.7, instance=0, **kw),
+            S.Job(8, 0.5, instance=1, kind="aniso", Kc=0.05, theta=40.0, phi=45.0, **kw),
+            S.Job(0, 0.9, instance=2, kind="film", shape=(12, 10, 3), diameter=4.0, **kw)]
+    done = S.Server(precision=64, quantum=7).run(jobs)
+    assert len(done) == 3
+    for j in sorted(done, key=lambda j: j.instance):
+        last = j.reads[-1]
+        if j.kind == "mt":
+            o = O.OracleLattice(*j.shape, J=1.0, Ku=j.Ku, eu=(0, 0, 1), seed=j.seed, instance=j.instance,
+                                init="aligned")
+            o.sweep(j.T, j.equil)
+            o.sweep(j.T, j.samples, sample=True)
+        elif j.kind == "aniso":
+            o = O.OracleLattice(*j.shape, J=1.0, Kc=j.Kc, seed=j.seed, instance=j.instance, init="aligned",
+                                init_dir=j.e_c())
+            o.constrained_sweep(j.T, j.e_c(), j.equil)
+            o.constrained_sweep(j.T, j.e_c(), j.samples, sample=True)
+        else:
+            o = O.OracleLattice(*j.shape, J=1.0, Ku=j.Ku, eu=(0, 0, 1), seed=j.seed, instance=j.instance,
+                                init="aligned", boundary_z="open")
+            g, _ = F.voronoi_grains(j.shape[0], j.shape[1], j.diameter, j.grain_seed)
+            o.set_bond_masks(F.grain_bond_masks(g, j.shape[2]))
+            o.sweep(j.T, j.equil)
+            o.sweep(j.T, j.samples, sample=True)
+        ref = o.observables(j.T)
+        _say(j.kind, "served <|m|>", last["mean_m"][0], "reference", ref["mean_m"][0])
+        assert last["sweeps_done"] == j.total and last["samples"] == j.samples
+        assert last["theta_deg"] == o.counters()[0]
+        assert np.allclose(last["mean_m"], ref["mean_m"], rtol=1e-11, atol=1e-13), j.kind
+        assert abs(last["mean_E"] - ref["mean_E"]) < 1e-11 * max(1.0, abs(ref["mean_E"])), j.kind
+        assert abs(last["mean_Eanis"] - ref["mean_Eanis"]) < 1e-12, j.kind
+        if j.kind == "aniso":
+            assert np.allclose(last["mean_torque"], ref["mean_torque"], rtol=1e-9, atol=1e-12)
+            assert j.result["se_g"] >= 0 and abs(j.result["g"] + np.dot(ref["mean_torque"],
+                                                                        [-np.sin(np.pi / 4), np.cos(np.pi / 4), 0])) < 1e-9
