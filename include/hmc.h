@@ -256,7 +256,7 @@ int hmc_read_timing(hmc_lattice* L, hmc_timing* out);
  * m = |M|/N, the energy terms of Eq. 2 with every bond once, the anisotropy
  * torque), on spins held by the caller and without a lattice handle or a
  * workspace.  The reduction scratch (per-work-group partials and the reduced
- * values) lives in a static device array of the library: 6.5 MiB per GPU,
+ * values) lives in a static device array of the library: 6.51 MiB per GPU,
  * held from the first call on that GPU until the process ends.
  *   p:         the lattice's parameters (validated as by hmc_init_lattice;
  *              bond_masks must be 0);

@@ -169,7 +169,9 @@ Layout layout_for(const hmc_params* p)
     off += align_up(181 * sizeof(double) + 181 * sizeof(float), hmc::kAlign);
     L.max_blocks = hmc::max_blocks_for(p->nx, p->ny, p->nz);
     L.off_part = off;
-    off += align_up((size_t)L.max_blocks * hmc::kNumPart * sizeof(double), hmc::kAlign);
+    // kNumPart rows of max_blocks partials, then the group sums of the fold
+    off += align_up(((size_t)L.max_blocks + (size_t)hmc::fold_groups_for(L.max_blocks)) * hmc::kNumPart *
+                        sizeof(double), hmc::kAlign);
     L.off_cnt = off;
     off += align_up((size_t)L.max_blocks * 2 * sizeof(uint32_t), hmc::kAlign);
     L.off_mask = off;

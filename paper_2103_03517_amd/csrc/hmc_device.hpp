@@ -234,6 +234,43 @@ struct Acc {
     double tq[3] = {0.0, 0.0, 0.0};
 };
 
+// A thread's sums of its sampled site terms over its z chunk of a colour
+// pass (z_chunk x sites-per-thread terms), kept in the spin precision and
+// converted to FP64 once per chunk; no FP64 register is live in the march.
+// The chunk sums carry FP32 rounding of the order of the site terms' own
+// (relative 1e-7 times the square root of the number of terms).
+template <typename R>
+struct Part {
+    R M[3] = {R(0), R(0), R(0)};
+    R ex = R(0), eu = R(0), ec = R(0), ez = R(0);
+};
+
+// The accumulator the pass adds site terms to: the partial sums for FP32
+// spins, the FP64 Acc itself for FP64 spins.
+template <typename R>
+__device__ __forceinline__ auto& site_acc(Acc& a, Part<R>& p)
+{
+    if constexpr (sizeof(R) == 4) return p;
+    else return a;
+}
+
+// Adds the partial sums into the FP64 accumulator and clears them (nothing
+// to do when the pass adds to Acc directly).
+template <typename A>
+__device__ __forceinline__ void flush_part(Acc& acc, A& p)
+{
+    if constexpr (!__is_same(A, Acc)) {
+        acc.M[0] += (double)p.M[0];
+        acc.M[1] += (double)p.M[1];
+        acc.M[2] += (double)p.M[2];
+        acc.ex += (double)p.ex;
+        acc.eu += (double)p.eu;
+        acc.ec += (double)p.ec;
+        acc.ez += (double)p.ez;
+        p = A{};
+    }
+}
+
 // Adds the one-site terms of s (anisotropy, Zeeman, moment) and, when
 // TORQUE, s x (-dE_anis/ds).
 template <typename R, bool TORQUE>

@@ -65,7 +65,7 @@ struct DevLattice {
     const void* c1tab;        // 181 reals: 1 - cos(theta) for theta in degrees
     void* aos;                // constrained sweeps: [colour][Nc] 4-vectors of the spins, then [Nc]
                               // records (spin, neighbour sum) of the colour being paired
-    double* part;             // [max_blocks][kNumPart]
+    double* part;             // [kNumPart][max_blocks]: work-group partials, one row per component
     uint32_t* cnt;            // [2][max_blocks]
     int64_t max_blocks;
     double J, Ku, eu[3], Kc, h[3];
@@ -118,6 +118,9 @@ int64_t pass_blocks(const DevLattice& d, int spt, int zc);
 size_t pass_lds_bytes(int precision, int hx, int spt);
 // Largest partial count any launch can need.
 int64_t max_blocks_for(int32_t nx, int32_t ny, int32_t nz);
+// Groups of 1024 records the finalize folds for n work-group records; the
+// workspace holds this many group sums after the partial rows.
+inline int64_t fold_groups_for(int64_t n) { return (n + 1023) / 1024; }
 
 // Batches.  The table of a batch holds one entry per lattice (kernel
 // arguments and launch shape), built on the host by batch_fill_entry.  The

@@ -24,12 +24,28 @@ size_t pass_lds_bytes(int precision, int hx, int spt)
     return b < 1024 ? 1024 : b;
 }
 
-__global__ __launch_bounds__(kThreads) void finalize_kernel(DevState* st, const double* part, const uint32_t* cnt,
-                                                            uint32_t cnt_stride, uint32_t nred, uint32_t nblack,
-                                                            uint32_t npart, int fin, double T, double N)
+// The per-sweep finalize, one work-group of 1024 threads: all of them sum
+// the counts, the first 256 fold the records (or the group sums left by
+// fold_groups_kernel in l2).  A lone work-group has no occupancy to gain, so
+// the register budget of four waves per SIMD goes to loads in flight.
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void finalize_kernel(DevState* st, const double* part, uint32_t stride, const uint32_t* cnt, uint32_t nred,
+                     uint32_t nblack, uint32_t npart, const double* l2, int fin, double T, double N)
 {
-    __shared__ double scratch[5 * (kNumPart + 1)];
-    finalize_body(st, part, cnt, cnt_stride, nred, nblack, npart, fin, T, N, scratch);
+    __shared__ double scratch[kFinScratch];
+    __shared__ DevState sst;
+    finalize_body<1024>(st, part, stride, cnt, nred, nblack, npart, l2, fin, T, N, scratch, &sst);
+}
+
+// Work-group g: the sum S_g of record group g (the order of finalize_body),
+// stored at l2[g * kNumPart ..].
+__global__ __launch_bounds__(kGroupThreads) void fold_groups_kernel(const double* part, uint32_t stride,
+                                                                    uint32_t npart, double* l2)
+{
+    __shared__ double scratch[5 * kNumPart];
+    group_sum(part, stride, npart, blockIdx.x, scratch, scratch + 4 * kNumPart);
+    if (threadIdx.x < (uint32_t)kNumPart)
+        l2[(size_t)blockIdx.x * kNumPart + threadIdx.x] = scratch[4 * kNumPart + threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -290,9 +306,13 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void finalize_records_kernel(const KArgs<R> a, const Vec4<R>* aos, Rec<R>* rec,
                                                                     uint32_t nrec, int fin, double T, double N)
 {
-    __shared__ double scratch[5 * (kNumPart + 1)];
+    // the pair passes write at most 2 x HMC_PAIR_BLOCKS records: one group
+    static_assert(2 * HMC_PAIR_BLOCKS <= kGroupRecords, "the fused finalize folds one group of records");
+    __shared__ double scratch[kFinScratch];
+    __shared__ DevState sst;
     if (blockIdx.x == 0) {
-        finalize_body(a.st, a.part, a.cnt, a.cnt_stride, nrec, nrec, 2 * nrec, fin, T, N, scratch);
+        finalize_body<kThreads>(a.st, a.part, a.cnt_stride, a.cnt, nrec, nrec, 2 * nrec, nullptr, fin, T, N, scratch,
+                                &sst);
         return;
     }
     records_range<R, 0>(a, aos, rec, blockIdx.x - 1, gridDim.x - 1);
@@ -477,7 +497,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R
     }
     if (t < held) pair_move<R, C, OBS>(x, own, qk[t], qa[t], qj[t], rec[qa[t]], rec[qj[t]], nacc, acc);
     KArgs<R> ra = a;
-    ra.part = a.part + (size_t)part_base * kNumPart;
+    ra.part = a.part + part_base;
     block_end<R, OBS>(ra, C, blockIdx.x, nacc, acc, scratch);
 }
 
@@ -666,8 +686,17 @@ hipError_t launch_measure(const DevLattice& d, hipStream_t s, int64_t* blocks)
 hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t black_blocks, int64_t part_blocks,
                            int fin, double T, hipStream_t s)
 {
-    finalize_kernel<<<1, kThreads, 0, s>>>(d.st, d.part, d.cnt, (uint32_t)d.max_blocks, (uint32_t)red_blocks,
-                                            (uint32_t)black_blocks, (uint32_t)part_blocks, fin, T, (double)d.N);
+    const uint32_t stride = (uint32_t)d.max_blocks;
+    const uint32_t G = (uint32_t)cdiv((uint64_t)part_blocks, (uint64_t)kGroupRecords);
+    const double* l2 = nullptr;
+    if ((fin & kFinObs) && G > 1) {
+        // the group sums, in parallel, into the space after the partial rows
+        double* g2 = d.part + (size_t)kNumPart * stride;
+        fold_groups_kernel<<<G, kGroupThreads, 0, s>>>(d.part, stride, (uint32_t)part_blocks, g2);
+        l2 = g2;
+    }
+    finalize_kernel<<<1, 1024, 0, s>>>(d.st, d.part, stride, d.cnt, (uint32_t)red_blocks, (uint32_t)black_blocks,
+                                       (uint32_t)part_blocks, l2, fin, T, (double)d.N);
     return hipGetLastError();
 }
 

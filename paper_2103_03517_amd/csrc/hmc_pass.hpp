@@ -40,7 +40,7 @@ struct KArgs {
     const R* c1tab;
     double* part;
     uint32_t* cnt;       // [2][cnt_stride]
-    uint32_t cnt_stride;
+    uint32_t cnt_stride; // row stride of cnt and of part ([kNumPart][cnt_stride] doubles)
     uint32_t zbound;     // z boundary: 0 periodic, 1 anti-periodic, 2 open
     const uint8_t* mask[2];  // per colour, Nc bytes of active-bond bits (x-, x+, y-, y+, z-, z+), or null
 };
@@ -209,17 +209,63 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nblk)
 }
 
 // ---------------------------------------------------------------------------
-// Fixed-order reductions.  Within a wave a butterfly, across the four waves
-// of a work-group in wave order, across work-groups by the finalize kernel,
-// each thread taking work-groups t, t+256, ... in order.  The results
-// therefore do not depend on scheduling.
+// Fixed-order reductions.  Within a wave a DPP tree, across the four waves
+// of a work-group in wave order, across work-groups by the finalize kernel in
+// the order set out at finalize_body.  The results therefore do not depend
+// on scheduling.
 // ---------------------------------------------------------------------------
+// Cross-lane moves for the wave sum: DPP row operations (gfx9 encodings),
+// which run on the vector ALU instead of the LDS crossbar.
+constexpr int kDppQuadSwap1 = 0xB1;        // quad_perm [1,0,3,2]: lane i takes lane i ^ 1
+constexpr int kDppQuadSwap2 = 0x4E;        // quad_perm [2,3,0,1]: lane i takes lane i ^ 2
+constexpr int kDppRowHalfMirror = 0x141;   // lane i takes lane 7 - i within its 8-lane half-row
+constexpr int kDppRowMirror = 0x140;       // lane i takes lane 15 - i within its 16-lane row
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T v)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, dpp_u32<CTRL>(__builtin_bit_cast(uint32_t, v)));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint64_t lo = dpp_u32<CTRL>((uint32_t)u), hi = dpp_u32<CTRL>((uint32_t)(u >> 32));
+        return __builtin_bit_cast(T, lo | (hi << 32));
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int lane)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, (uint32_t)__builtin_amdgcn_readlane((int)__builtin_bit_cast(uint32_t, v), lane));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+        const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+        return __builtin_bit_cast(T, lo | (hi << 32));
+    }
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), the same on every
+// lane: pairs, quads, half-rows and rows by DPP moves (at each step the two
+// lanes of a pair add the same two values, so they hold the same sum), then
+// the four row sums as (row0 + row1) + (row2 + row3).
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_move<kDppQuadSwap1>(v);
+    v += dpp_move<kDppQuadSwap2>(v);
+    v += dpp_move<kDppRowHalfMirror>(v);
+    v += dpp_move<kDppRowMirror>(v);
+    const T r0 = read_lane(v, 0), r1 = read_lane(v, 16), r2 = read_lane(v, 32), r3 = read_lane(v, 48);
+    return (r0 + r1) + (r2 + r3);
 }
 
 // Sums NV values over the work-group; the totals land in scratch[0..NV).
@@ -243,7 +289,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch)
 }
 
 // The end of a producing launch: work-group b writes its acceptance count
-// and (OBS) its partial sums.  They are reduced by finalize_kernel, launched
+// and (OBS) its partial sums, component e at part[e * cnt_stride + b] (one
+// row per component, so the finalize reads each row coalesced).  They are reduced by finalize_kernel, launched
 // next on the same stream (the kernel boundary makes them visible).
 template <typename R, bool OBS>
 __device__ __forceinline__ void block_end(const KArgs<R>& a, int colour, uint32_t b, uint32_t nacc, const Acc& acc,
@@ -253,7 +300,7 @@ __device__ __forceinline__ void block_end(const KArgs<R>& a, int colour, uint32_
         double v[kNumPart] = {acc.M[0], acc.M[1], acc.M[2], acc.ex, acc.eu, acc.ec, acc.ez,
                               acc.tq[0], acc.tq[1], acc.tq[2], (double)nacc, 0.0};
         block_sum<kNumPart>(v, scratch);
-        if (threadIdx.x < kNumPart) a.part[(size_t)b * kNumPart + threadIdx.x] = scratch[threadIdx.x];
+        if (threadIdx.x < kNumPart) a.part[(size_t)threadIdx.x * a.cnt_stride + b] = scratch[threadIdx.x];
         if (threadIdx.x == 0) a.cnt[(size_t)colour * a.cnt_stride + b] = (uint32_t)scratch[10];
     } else {
         uint32_t c = wave_sum(nacc);
@@ -270,85 +317,148 @@ __device__ __forceinline__ void block_end(const KArgs<R>& a, int colour, uint32_
 }
 
 // ---------------------------------------------------------------------------
-// Per-sweep finalize (one work-group): the fixed-order reduction of the
-// work-group results of the colour-1 (and, for the counts, colour-0) launch,
-// then Table A1's cone-angle rule (one degree up when accepted/N > 1/2, else
-// down, within [1, 180]), the sweep counter and on sampled sweeps the
-// shifted FP64 accumulators of Eq. 6.
+// Per-sweep finalize: the fixed-order reduction of the work-group results of
+// the colour-1 (and, for the counts, colour-0) launch, then Table A1's
+// cone-angle rule (one degree up when accepted/N > 1/2, else down, within
+// [1, 180]), the sweep counter and on sampled sweeps the shifted FP64
+// accumulators of Eq. 6.
+//
+// The records are folded in one order, whichever kernel folds them.  They
+// form groups of 1024 (group g: records 1024g .. 1024g + 1023).  In a group,
+// thread t of 256 adds records 1024g + t, + 256, + 512 and + 768 in turn
+// (from 0.0); wave_sum adds the threads of each wave and the four wave sums
+// are added in wave order (from 0.0), giving the group sum S_g.  The total is
+// ((0.0 + S_0) + S_1) + ... .  A group is one round of loads (48 per thread).
+// With more than one group the single-lattice path computes the group sums
+// in parallel (fold_groups_kernel, one work-group per group) and the
+// finalize adds them; the batch finalize computes them one after the other.
+// The counts are integers, summed in any order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void finalize_body(DevState* st, const double* part, const uint32_t* cnt,
-                                              uint32_t cnt_stride, uint32_t nred, uint32_t nblack, uint32_t npart,
-                                              int fin, double T, double N, double* scratch)
+constexpr int kGroupRecords = 1024;
+constexpr int kGroupThreads = 256;
+// doubles of shared memory finalize_body needs: the wave sums [4][kNumPart],
+// the totals [kNumPart + 1] and the per-wave counts [16]
+constexpr int kFinScratch = 4 * kNumPart + kNumPart + 1 + 16;
+
+// S_g of group g into sg[0..kNumPart) (shared memory).  Every thread of the
+// work-group calls it (it holds barriers); threads 0..255 do the work.
+__device__ __forceinline__ void group_sum(const double* part, uint32_t stride, uint32_t npart, uint32_t g,
+                                          double* wsum, double* sg)
 {
     const uint32_t t = threadIdx.x;
-    double v[kNumPart + 1];
+    if (t < (uint32_t)kGroupThreads) {
+        const uint32_t r0 = g * (uint32_t)kGroupRecords + t;
+        double q[4][kNumPart];
 #pragma unroll
-    for (int i = 0; i <= kNumPart; ++i) v[i] = 0.0;
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t r = r0 + (uint32_t)(u * kGroupThreads);
+            const double* p = part + (r < npart ? r : 0u);     // record 0 always exists
+#pragma unroll
+            for (int e = 0; e < kNumPart; ++e) q[u][e] = p[(size_t)e * stride];
+        }
+        // a record past the end adds +0.0, which changes no sum (no partial
+        // sum here is ever -0.0), so the loads need no branch
+        double v[kNumPart];
+#pragma unroll
+        for (int e = 0; e < kNumPart; ++e) v[e] = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool in = r0 + (uint32_t)(u * kGroupThreads) < npart;
+#pragma unroll
+            for (int e = 0; e < kNumPart; ++e) v[e] += in ? q[u][e] : 0.0;
+        }
+        // all wave sums first, then one branch for the stores
+#pragma unroll
+        for (int e = 0; e < kNumPart; ++e) v[e] = wave_sum(v[e]);
+        if ((t & 63u) == 0) {
+#pragma unroll
+            for (int e = 0; e < kNumPart; ++e) wsum[(t >> 6) * kNumPart + e] = v[e];
+        }
+    }
+    __syncthreads();
+    if (t < (uint32_t)kNumPart) {
+        double x = 0.0;
+        for (int w = 0; w < kGroupThreads / 64; ++w) x += wsum[w * kNumPart + t];
+        sg[t] = x;
+    }
+    __syncthreads();
+}
+
+// The finalize of one lattice by one work-group of NT threads (256 or 1024).
+// stride: row stride of part and cnt; l2: the group sums computed by
+// fold_groups_kernel ([G][kNumPart]), or null when this work-group computes
+// them.  sst: shared memory for a copy of the chain state, read at the start
+// so that the state update at the end does not wait for global memory.
+template <int NT>
+__device__ __forceinline__ void finalize_body(DevState* st, const double* part, uint32_t stride, const uint32_t* cnt,
+                                              uint32_t nred, uint32_t nblack, uint32_t npart, const double* l2,
+                                              int fin, double T, double N, double* scratch, DevState* sst)
+{
+    static_assert(NT >= kGroupThreads && NT % 64 == 0 && NT <= 1024, "work-group size");
+    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
+    double* wsum = scratch;                                                   // [4][kNumPart]
+    double* tot = scratch + 4 * kNumPart;                                     // [kNumPart + 1]
+    unsigned long long* wc = reinterpret_cast<unsigned long long*>(tot + kNumPart + 1);   // [NT / 64]
+    // the last wave takes no part in the record fold: one of its threads
+    // copies the chain state while the others fold
+    if (t == (uint32_t)NT - 1) *sst = *st;
     if (fin & kFinCounts) {
-        // integer sums: any order gives the same total; four loads in flight
+        // integer sums: any order gives the same total; eight loads in flight
+        constexpr int UC = 8;
+        const uint32_t nc = nred + nblack;
         unsigned long long c = 0;
-        for (uint32_t i = t; i < nred; i += 4 * kThreads) {
-            uint32_t w[4];
+        for (uint32_t i = t; i < nc; i += UC * NT) {
+            uint32_t w[UC];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t j = i + (uint32_t)u * kThreads;
-                const uint32_t x = cnt[j < nred ? j : i];     // always in range
-                w[u] = j < nred ? x : 0u;
+            for (int u = 0; u < UC; ++u) {
+                const uint32_t j = i + (uint32_t)u * NT;
+                const uint32_t jj = j < nc ? j : i;                    // always in range
+                const uint32_t x = jj < nred ? cnt[jj] : cnt[stride + (jj - nred)];
+                w[u] = j < nc ? x : 0u;
             }
-            c += (unsigned long long)w[0] + w[1] + w[2] + w[3];
-        }
-        for (uint32_t i = t; i < nblack; i += 4 * kThreads) {
-            uint32_t w[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t j = i + (uint32_t)u * kThreads;
-                const uint32_t x = cnt[cnt_stride + (j < nblack ? j : i)];
-                w[u] = j < nblack ? x : 0u;
-            }
-            c += (unsigned long long)w[0] + w[1] + w[2] + w[3];
+            for (int u = 0; u < UC; ++u) c += w[u];
         }
-        v[kNumPart] = (double)c;
+        c = wave_sum(c);
+        if (lane == 0) wc[wave] = c;
     }
     if (fin & kFinObs) {
-        // each thread takes whole 96-byte records t, t + 256, t + 512, ...:
-        // the loads of four records are issued together (the loop is bound by
-        // their latency), then added in record order, so the sums are those
-        // of a plain record-by-record loop
-        // (a record past the end is read at i0 and added as +0.0, which
-        // leaves every sum unchanged, so there is no branch in the loop)
-        constexpr int U = 4;
-        for (uint32_t i0 = t; i0 < npart; i0 += U * kThreads) {
-            double2 q[U][kNumPart / 2];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t i = i0 + (uint32_t)u * kThreads;
-                const double2* p = reinterpret_cast<const double2*>(part + (size_t)(i < npart ? i : i0) * kNumPart);
-#pragma unroll
-                for (int k = 0; k < kNumPart / 2; ++k) q[u][k] = p[k];
+        const uint32_t G = (npart + (uint32_t)kGroupRecords - 1u) / (uint32_t)kGroupRecords;
+        if (l2 != nullptr) {
+            if (t < (uint32_t)kNumPart) {
+                double x = 0.0;
+                for (uint32_t g = 0; g < G; ++g) x += l2[(size_t)g * kNumPart + t];
+                tot[t] = x;
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool in = i0 + (uint32_t)u * kThreads < npart;
-#pragma unroll
-                for (int k = 0; k < kNumPart / 2; ++k) {
-                    v[2 * k] += in ? q[u][k].x : 0.0;
-                    v[2 * k + 1] += in ? q[u][k].y : 0.0;
-                }
+        } else {
+            double run = 0.0;          // threads 0..kNumPart-1: the running total
+            for (uint32_t g = 0; g < G; ++g) {
+                group_sum(part, stride, npart, g, wsum, tot);
+                if (t < (uint32_t)kNumPart) run += tot[t];
             }
+            if (t < (uint32_t)kNumPart) tot[t] = run;
         }
     }
-    block_sum<kNumPart + 1>(v, scratch);
+    __syncthreads();
+    if ((fin & kFinCounts) && t == (uint32_t)kNumPart) {
+        unsigned long long c = 0;
+        for (int w = 0; w < NT / 64; ++w) c += wc[w];
+        tot[kNumPart] = (double)c;
+    }
+    __syncthreads();
     if (t != 0) return;
-    const double* tot = scratch;
+    const DevState& cur = *sst;
     if (fin & kFinCounts) {
         const long long accepted = (long long)tot[kNumPart];
         st->accepted_last = accepted;
+        int32_t th = cur.theta;
         if (2.0 * (double)accepted > N) {
-            if (st->theta < 180) st->theta += 1;
+            if (th < 180) th += 1;
         } else {
-            if (st->theta > 1) st->theta -= 1;
+            if (th > 1) th -= 1;
         }
-        st->sweep += 1;
+        st->theta = th;
+        st->sweep = cur.sweep + 1;
     }
     if (fin & kFinObs) {
         bool finite = true;
@@ -373,19 +483,20 @@ __device__ __forceinline__ void finalize_body(DevState* st, const double* part, 
             x[3] = tot[kMz] / N;
             x[0] = sqrt(x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
             x[4] = (tot[kEexch] + tot[kEuni] + tot[kEcub] + tot[kEzee]) / N;
-            if (st->samples == 0)
-                for (int i = 0; i < 5; ++i) st->shift[i] = x[i];
+            const bool first = cur.samples == 0;
             for (int i = 0; i < 5; ++i) {
-                const double d = x[i] - st->shift[i];
-                st->sum[i] += d;
-                st->sum2[i] += d * d;
+                const double sh = first ? x[i] : cur.shift[i];
+                if (first) st->shift[i] = x[i];
+                const double d = x[i] - sh;
+                st->sum[i] = cur.sum[i] + d;
+                st->sum2[i] = cur.sum2[i] + d * d;
             }
-            st->sum_eanis += (tot[kEuni] + tot[kEcub]) / N;
+            st->sum_eanis = cur.sum_eanis + (tot[kEuni] + tot[kEcub]) / N;
             if (fin & kFinTorque) {
-                for (int i = 0; i < 3; ++i) st->sum_torque[i] += tot[kTx + i] / N;
-                st->torque_samples += 1;
+                for (int i = 0; i < 3; ++i) st->sum_torque[i] = cur.sum_torque[i] + tot[kTx + i] / N;
+                st->torque_samples = cur.torque_samples + 1;
             }
-            st->samples += 1;
+            st->samples = cur.samples + 1;
             st->T_sample = T;
         }
     }
@@ -396,10 +507,10 @@ __device__ __forceinline__ void finalize_body(DevState* st, const double* part, 
 // energy change in the local field, acceptance P < exp(-dE/T).  Returns the
 // final spin; OBS adds the site and its red x-partner to the observables.
 // ---------------------------------------------------------------------------
-template <typename R, bool OBS>
+template <typename R, bool OBS, typename A>
 __device__ __forceinline__ V3<R> update_site(const Model<R>& m, const V3<R>& s, const V3<R>& nb,
                                              const V3<R>& partner, const Rand4& rn, R c1, R scale,
-                                             uint32_t& nacc, Acc& acc)
+                                             uint32_t& nacc, A& acc)
 {
     const V3<R> hl{m.J * nb.x + m.h.x, m.J * nb.y + m.h.y, m.J * nb.z + m.h.z};
     const V3<R> tr = cone_move(s, Prim<R>::u01(rn.r0), Prim<R>::u01(rn.r1), c1);
@@ -409,17 +520,18 @@ __device__ __forceinline__ V3<R> update_site(const Model<R>& m, const V3<R>& s, 
     const V3<R> f = ok ? tr : s;
     nacc += ok ? 1u : 0u;
     if (OBS) {
+        // acc is the FP64 Acc (FP64 spins) or the spin-precision partial sums
         const V3<R> fp{f.x + partner.x, f.y + partner.y, f.z + partner.z};
-        acc.M[0] += (double)fp.x;
-        acc.M[1] += (double)fp.y;
-        acc.M[2] += (double)fp.z;
-        acc.ex += (double)(-m.J * dot(f, nb));
+        acc.M[0] += fp.x;
+        acc.M[1] += fp.y;
+        acc.M[2] += fp.z;
+        acc.ex += -m.J * dot(f, nb);
         if (m.Ku != R(0)) {
             const R sf = ok ? k.te : k.se, sp = dot(partner, m.e);
-            acc.eu += (double)(-m.Ku * (sf * sf + sp * sp));
+            acc.eu += -m.Ku * (sf * sf + sp * sp);
         }
-        if (m.Kc != R(0)) acc.ec += (double)(m.Kc * ((ok ? k.ct : k.cs) + cubic_f(partner)));
-        acc.ez += (double)(-dot(m.h, fp));
+        if (m.Kc != R(0)) acc.ec += m.Kc * ((ok ? k.ct : k.cs) + cubic_f(partner));
+        if (m.h.x != R(0) || m.h.y != R(0) || m.h.z != R(0)) acc.ez += -dot(m.h, fp);
     }
     return f;
 }
@@ -448,7 +560,9 @@ __device__ __forceinline__ V3<R> update_site(const Model<R>& m, const V3<R>& s, 
 // OBS (black pass only) fuses the observables: the black site after its
 // update plus its red x-partner (same colour index), and the exchange of the
 // black site with its six final red neighbours, so every site and every bond
-// is counted once.
+// is counted once.  With FP32 spins a thread sums these terms in FP32 over
+// its z chunk (z_chunk x SPT sites) and converts the sums to FP64 once;
+// everything above the thread is FP64.
 // ---------------------------------------------------------------------------
 template <typename R, int SPT, int HALO>
 struct PassCtx {
@@ -470,11 +584,11 @@ struct PassCtx {
 // op, opp hold the other colour's z-1, z, z+1 and z+2 (in flight), sc and
 // sn the own colour's z and z+1 (in flight), hp and hpp the halo's z+1 and
 // z+2 (in flight).
-template <typename R, int C, bool OBS, int SPT, int HALO, int K, bool MASK>
+template <typename R, int C, bool OBS, int SPT, int HALO, int K, bool MASK, typename A>
 __device__ __forceinline__ void step1(const KArgs<R>& a, const Arrays<R>& g, const PassCtx<R, SPT, HALO>& x,
                                           uint32_t zi, V3<R> (&om)[SPT], V3<R> (&o0)[SPT], V3<R> (&op)[SPT],
                                           V3<R> (&opp)[SPT], V3<R> (&sc)[SPT], V3<R> (&sn)[SPT],
-                                          V3<R> (&hp)[HALO], V3<R> (&hpp)[HALO], uint32_t& nacc, Acc& acc)
+                                          V3<R> (&hp)[HALO], V3<R> (&hpp)[HALO], uint32_t& nacc, A& acc)
 {
     constexpr int O = 1 - C;
     constexpr int B = K & 1;
@@ -585,16 +699,19 @@ __device__ __forceinline__ void march1(const KArgs<R>& a, const Arrays<R>& g, co
     }
     __syncthreads();
 
+    Part<R> part;
+    auto& pa = site_acc<R>(acc, part);
     uint32_t zi = 0;
     for (; zi + 4 <= x.zn; zi += 4) {
-        step1<R, C, OBS, SPT, HALO, 0, MASK>(a, g, x, zi + 0, rA, rB, rC, rD, s0, s1, h0, h1, nacc, acc);
-        step1<R, C, OBS, SPT, HALO, 1, MASK>(a, g, x, zi + 1, rB, rC, rD, rA, s1, s0, h1, h0, nacc, acc);
-        step1<R, C, OBS, SPT, HALO, 2, MASK>(a, g, x, zi + 2, rC, rD, rA, rB, s0, s1, h0, h1, nacc, acc);
-        step1<R, C, OBS, SPT, HALO, 3, MASK>(a, g, x, zi + 3, rD, rA, rB, rC, s1, s0, h1, h0, nacc, acc);
+        step1<R, C, OBS, SPT, HALO, 0, MASK>(a, g, x, zi + 0, rA, rB, rC, rD, s0, s1, h0, h1, nacc, pa);
+        step1<R, C, OBS, SPT, HALO, 1, MASK>(a, g, x, zi + 1, rB, rC, rD, rA, s1, s0, h1, h0, nacc, pa);
+        step1<R, C, OBS, SPT, HALO, 2, MASK>(a, g, x, zi + 2, rC, rD, rA, rB, s0, s1, h0, h1, nacc, pa);
+        step1<R, C, OBS, SPT, HALO, 3, MASK>(a, g, x, zi + 3, rD, rA, rB, rC, s1, s0, h1, h0, nacc, pa);
     }
-    if (zi < x.zn) step1<R, C, OBS, SPT, HALO, 0, MASK>(a, g, x, zi + 0, rA, rB, rC, rD, s0, s1, h0, h1, nacc, acc);
-    if (zi + 1 < x.zn) step1<R, C, OBS, SPT, HALO, 1, MASK>(a, g, x, zi + 1, rB, rC, rD, rA, s1, s0, h1, h0, nacc, acc);
-    if (zi + 2 < x.zn) step1<R, C, OBS, SPT, HALO, 2, MASK>(a, g, x, zi + 2, rC, rD, rA, rB, s0, s1, h0, h1, nacc, acc);
+    if (zi < x.zn) step1<R, C, OBS, SPT, HALO, 0, MASK>(a, g, x, zi + 0, rA, rB, rC, rD, s0, s1, h0, h1, nacc, pa);
+    if (zi + 1 < x.zn) step1<R, C, OBS, SPT, HALO, 1, MASK>(a, g, x, zi + 1, rB, rC, rD, rA, s1, s0, h1, h0, nacc, pa);
+    if (zi + 2 < x.zn) step1<R, C, OBS, SPT, HALO, 2, MASK>(a, g, x, zi + 2, rC, rD, rA, rB, s0, s1, h0, h1, nacc, pa);
+    if constexpr (OBS) flush_part(acc, pa);
 
 }
 
@@ -609,12 +726,12 @@ __device__ __forceinline__ void march1(const KArgs<R>& a, const Arrays<R>& g, co
 // (the compiler's wait counts are then those of the steady state); the
 // planes are clamped to the last one the tile needs, so the loads of the
 // last steps re-read planes just fetched.
-template <typename R, int C, bool OBS, int SPT, int HALO, bool MASK>
+template <typename R, int C, bool OBS, int SPT, int HALO, bool MASK, typename A>
 __device__ __forceinline__ void step2(const KArgs<R>& a, const Arrays<R>& g, const PassCtx<R, SPT, HALO>& x,
                                           uint32_t zi, V3<R> (&om)[SPT], V3<R> (&op)[SPT], V3<R> (&on)[SPT],
                                           V3<R> (&sc)[SPT], V3<R> (&sn)[SPT], V3<R> (&hp)[HALO],
                                           V3<R> (&hn)[HALO], uint32_t (&mc)[SPT], uint32_t (&mn)[SPT],
-                                          uint32_t& nacc, Acc& acc)
+                                          uint32_t& nacc, A& acc)
 {
     constexpr int O = 1 - C;
     const uint32_t z = x.z0 + zi;
@@ -755,14 +872,17 @@ __device__ __forceinline__ void march2(const KArgs<R>& a, const Arrays<R>& g, co
     }
     __syncthreads();
 
+    Part<R> part;
+    auto& pa = site_acc<R>(acc, part);
     uint32_t zi = 0;
     for (; zi + 3 <= x.zn; zi += 3) {
-        step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 0, om, oA, oC, sA, sC, hA, hC, mA, mC, nacc, acc);
-        step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 1, om, oB, oA, sB, sA, hB, hA, mB, mA, nacc, acc);
-        step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 2, om, oC, oB, sC, sB, hC, hB, mC, mB, nacc, acc);
+        step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 0, om, oA, oC, sA, sC, hA, hC, mA, mC, nacc, pa);
+        step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 1, om, oB, oA, sB, sA, hB, hA, mB, mA, nacc, pa);
+        step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 2, om, oC, oB, sC, sB, hC, hB, mC, mB, nacc, pa);
     }
-    if (zi < x.zn) step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 0, om, oA, oC, sA, sC, hA, hC, mA, mC, nacc, acc);
-    if (zi + 1 < x.zn) step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 1, om, oB, oA, sB, sA, hB, hA, mB, mA, nacc, acc);
+    if (zi < x.zn) step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 0, om, oA, oC, sA, sC, hA, hC, mA, mC, nacc, pa);
+    if (zi + 1 < x.zn) step2<R, C, OBS, SPT, HALO, MASK>(a, g, x, zi + 1, om, oB, oA, sB, sA, hB, hA, mB, mA, nacc, pa);
+    if constexpr (OBS) flush_part(acc, pa);
 
 }
 

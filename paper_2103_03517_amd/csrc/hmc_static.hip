@@ -22,14 +22,14 @@
 namespace {
 
 // Largest lattice: 2^25 spins, so at most 2^24 sites per colour and
-// 2^24 / 256 = 65536 work-groups of the measurement, each writing one record
-// of kNumPart doubles and one count per colour row.
+// 2^24 / 256 = 65536 work-groups of the measurement, each writing one double
+// to each of the kNumPart partial rows and one count per colour row.
 constexpr uint64_t kStaticMaxSpins = 1ull << 25;
 constexpr size_t kStaticRecords = (kStaticMaxSpins / 2) / hmc::kThreads;
 constexpr size_t kStateBytes = (sizeof(hmc::DevState) + 255) / 256 * 256;
-constexpr size_t kPartBytes = kStaticRecords * hmc::kNumPart * sizeof(double);
+constexpr size_t kPartBytes = (kStaticRecords + kStaticRecords / 1024) * hmc::kNumPart * sizeof(double);
 constexpr size_t kCntBytes = 2 * kStaticRecords * sizeof(uint32_t);
-constexpr size_t kScratchBytes = kStateBytes + kPartBytes + kCntBytes;   // 6.5 MiB + 512 B
+constexpr size_t kScratchBytes = kStateBytes + kPartBytes + kCntBytes;   // 6822400 B (6.51 MiB)
 static_assert(kScratchBytes % 256 == 0, "scratch regions stay 256-byte aligned");
 
 }  // namespace
@@ -106,7 +106,7 @@ extern "C" int hmc_measure_static(const hmc_params* p, const void* dev_spins, si
     d.st = reinterpret_cast<hmc::DevState*>(sc);
     d.part = reinterpret_cast<double*>(sc + kStateBytes);
     d.cnt = reinterpret_cast<uint32_t*>(sc + kStateBytes + kPartBytes);
-    d.max_blocks = (int64_t)kStaticRecords;      // row stride of the counts
+    d.max_blocks = (int64_t)kStaticRecords;      // row stride of the counts and of the partials
     d.J = p->J;
     d.Ku = p->Ku;
     d.Kc = p->Kc;
