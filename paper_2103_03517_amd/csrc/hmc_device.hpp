@@ -243,6 +243,7 @@ template <typename R>
 struct Part {
     R M[3] = {R(0), R(0), R(0)};
     R ex = R(0), eu = R(0), ec = R(0), ez = R(0);
+    R tq[3] = {R(0), R(0), R(0)};
 };
 
 // The accumulator the pass adds site terms to: the partial sums for FP32
@@ -267,30 +268,34 @@ __device__ __forceinline__ void flush_part(Acc& acc, A& p)
         acc.eu += (double)p.eu;
         acc.ec += (double)p.ec;
         acc.ez += (double)p.ez;
+        acc.tq[0] += (double)p.tq[0];
+        acc.tq[1] += (double)p.tq[1];
+        acc.tq[2] += (double)p.tq[2];
         p = A{};
     }
 }
 
 // Adds the one-site terms of s (anisotropy, Zeeman, moment) and, when
-// TORQUE, s x (-dE_anis/ds).
-template <typename R, bool TORQUE>
-__device__ __forceinline__ void add_site(Acc& a, const Model<R>& m, const V3<R>& s)
+// TORQUE, s x (-dE_anis/ds), to the FP64 Acc or to spin-precision partial
+// sums (each term is formed in the spin precision either way).
+template <typename R, bool TORQUE, typename A>
+__device__ __forceinline__ void add_site(A& a, const Model<R>& m, const V3<R>& s)
 {
-    a.M[0] += (double)s.x;
-    a.M[1] += (double)s.y;
-    a.M[2] += (double)s.z;
+    a.M[0] += s.x;
+    a.M[1] += s.y;
+    a.M[2] += s.z;
     const R se = dot(s, m.e);
-    a.eu += (double)(-m.Ku * se * se);
-    a.ec += (double)(m.Kc * cubic_f(s));
-    a.ez += (double)(-dot(m.h, s));
+    a.eu += -m.Ku * se * se;
+    a.ec += m.Kc * cubic_f(s);
+    a.ez += -dot(m.h, s);
     if (TORQUE) {
         const R x2 = s.x * s.x, y2 = s.y * s.y, z2 = s.z * s.z;
         const R gx = R(2) * m.Ku * se * m.e.x - R(2) * m.Kc * s.x * (y2 + z2);
         const R gy = R(2) * m.Ku * se * m.e.y - R(2) * m.Kc * s.y * (x2 + z2);
         const R gz = R(2) * m.Ku * se * m.e.z - R(2) * m.Kc * s.z * (x2 + y2);
-        a.tq[0] += (double)(s.y * gz - s.z * gy);
-        a.tq[1] += (double)(s.z * gx - s.x * gz);
-        a.tq[2] += (double)(s.x * gy - s.y * gx);
+        a.tq[0] += s.y * gz - s.z * gy;
+        a.tq[1] += s.z * gx - s.x * gz;
+        a.tq[2] += s.x * gy - s.y * gx;
     }
 }
 

@@ -351,9 +351,9 @@ struct PairCtx {
 // acceptance both new spins go to the AoS copy.  OBS adds the one-site terms
 // of both final spins (and in the black pass their exchange with their final
 // red neighbours).
-template <typename R, int C, bool OBS>
+template <typename R, int C, bool OBS, typename A>
 __device__ __forceinline__ void pair_move(const PairCtx<R>& x, Vec4<R>* own, uint32_t k, uint32_t ia, uint32_t ja,
-                                          const Rec<R>& ri, const Rec<R>& rj, uint32_t& nacc, Acc& acc)
+                                          const Rec<R>& ri, const Rec<R>& rj, uint32_t& nacc, A& acc)
 {
     const Model<R>& m = x.m;
     const V3<R>& ec = x.ec;
@@ -387,7 +387,7 @@ __device__ __forceinline__ void pair_move(const PairCtx<R>& x, Vec4<R>* own, uin
         nacc += 2;
     }
     if (OBS) {
-        if (C == 1) acc.ex += (double)(-m.J * dot(fi, nbi)) + (double)(-m.J * dot(fj, nbj));
+        if (C == 1) acc.ex += (-m.J * dot(fi, nbi)) + (-m.J * dot(fj, nbj));
         add_site<R, true>(acc, m, fi);
         add_site<R, true>(acc, m, fj);
     }
@@ -439,6 +439,8 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R
     const uint32_t tiles = (a.Nc + kTrip - 1u) / kTrip;
     uint32_t nacc = 0;
     Acc acc;
+    Part<R> part;                                            // FP32 spins: the thread's sums, then FP64
+    auto& pa = site_acc<R>(acc, part);
     uint32_t held = 0;                                       // queued pairs, the same in every thread
     for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
 #pragma unroll
@@ -476,7 +478,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R
         for (; held - done >= kThreads; done += kThreads) {
             const uint32_t e = done + t;
             const uint32_t ia = qa[e], ja = qj[e];
-            pair_move<R, C, OBS>(x, own, qk[e], ia, ja, rec[ia], rec[ja], nacc, acc);
+            pair_move<R, C, OBS>(x, own, qk[e], ia, ja, rec[ia], rec[ja], nacc, pa);
         }
         // the rest of the queue (fewer than 256 pairs) to its front
         const uint32_t rest = held - done;
@@ -495,7 +497,8 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R
         held = rest;
         __syncthreads();
     }
-    if (t < held) pair_move<R, C, OBS>(x, own, qk[t], qa[t], qj[t], rec[qa[t]], rec[qj[t]], nacc, acc);
+    if (t < held) pair_move<R, C, OBS>(x, own, qk[t], qa[t], qj[t], rec[qa[t]], rec[qj[t]], nacc, pa);
+    if constexpr (OBS) flush_part(acc, pa);
     KArgs<R> ra = a;
     ra.part = a.part + part_base;
     block_end<R, OBS>(ra, C, blockIdx.x, nacc, acc, scratch);
