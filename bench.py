@@ -370,7 +370,7 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="run a few 256^3 FP32 sweeps and nothing else (for counter runs)")
     ap.add_argument("--profile-deep", action="store_true",
-                    help="only 10 sampled 384^3 FP32 sweeps (the two-plane march), for rocprofv3")
+                    help="only 60 sampled 384^3 FP32 sweeps (the two-plane march), for rocprofv3")
     ap.add_argument("--profile-constrained", action="store_true",
                     help="run a few 128^3 FP32 constrained sweeps and nothing else")
     ap.add_argument("--profile-batch", action="store_true",
@@ -408,9 +408,10 @@ def main():
         g = H.Lattice(384, 384, 384, precision=32, J=1.0, Ku=0.005, eu=(0, 0, 1), seed=7,
                       init="random")
         assert g.get_prefetch() == 2
-        g.sweep(1.0, 10, sample=True)
+        g.sweep(1.0, 60, sample=True)
         torch.cuda.synchronize()
-        log("profile-deep: 10 sampled 384^3 FP32 sweeps (20 colour passes, two planes of look-ahead)")
+        log(f"profile-deep: 60 sampled 384^3 FP32 sweeps (120 colour passes, two planes of look-ahead, "
+            f"launch shape {g.get_launch()})")
         return
     if args.serve_only:
         import json as _j
@@ -490,8 +491,10 @@ def main():
                 "traffic": (round(traffic) if traffic is not None else None),
                 "kernel": "pass_kernel<float> (one colour pass, 256^3)",
                 "algorithmic_bytes_per_launch": alg,
-                "note": "the 201 MB of spins stay in the 256 MB Infinity Cache; the pass is bound by its "
-                        "serial march over z (one plane of loads in flight per step), not by HBM or VALU",
+                "note": "frac is algorithmic bytes over the HBM peak; the 201 MB of spins stay in the 256 MB "
+                        "Infinity Cache, so this pass is bound by the latency of its serial march over z (one "
+                        "plane of loads in flight per step), not by HBM or VALU; the DRAM-bound figures are "
+                        "the pass_roofline entries of fp32_384cubed and fp32_464cubed",
                 "avg_launch_ms": round(pass_ms, 5)}
 
     # what a plain elementwise kernel reaches on the same bytes
@@ -565,7 +568,7 @@ def main():
                 "kernel": "pair_kernel<float> (one colour's pair moves, 128^3)",
                 "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(pair_ms, 5),
                 "note": "the 2 M-spin working set sits in the Infinity Cache; the pass is bound by its "
-                        "instruction issue (about 2450 VALU instructions per wave, waiting on memory 14 % of "
+                        "instruction issue (about 2600 VALU instructions per wave, waiting on memory 12-13 % of "
                         "the time) and one random line per partner record, not by HBM bandwidth"}
     line["kernel_timing"] = ("per-kernel averages from HIP events recorded by the library on the "
                              f"lattice's stream over a second region of {main_leg['kernel_timing_steps']} "

@@ -8,17 +8,19 @@ namespace hmc {
 // Finalize of a batch: work-group i folds the results of lattice i with its
 // own flags fin[i] (a lattice that does not sample ignores the partials of a
 // black pass that computed them for others).
+// (256 threads: the record fold of finalize_body needs no more, and the
+// lattices of a batch are small enough that the counts take a round or two)
 template <typename R>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
-void finalize_batch_kernel(const BatchEntry<R>* __restrict__ tab, const double* __restrict__ T,
-                           const int32_t* __restrict__ fin)
+__global__ __launch_bounds__(kThreads) void finalize_batch_kernel(const BatchEntry<R>* __restrict__ tab,
+                                                                  const double* __restrict__ T,
+                                                                  const int32_t* __restrict__ fin)
 {
     __shared__ double scratch[kFinScratch];
     __shared__ DevState sst;
     const BatchEntry<R>& E = tab[blockIdx.x];
     const int f = fin[blockIdx.x];
-    finalize_body<1024>(E.a.st, E.a.part, E.a.cnt_stride, E.a.cnt, E.nblk, E.nblk, (f & kFinObs) ? E.nblk : 0u,
-                        nullptr, f, T[blockIdx.x], E.N, scratch, &sst);
+    finalize_body<kThreads>(E.a.st, E.a.part, E.a.cnt_stride, E.a.cnt, E.nblk, E.nblk,
+                            (f & kFinObs) ? E.nblk : 0u, nullptr, f, T[blockIdx.x], E.N, scratch, &sst);
 }
 
 // Clears the accumulators of every lattice of a batch (work-group i, lattice
@@ -136,9 +138,9 @@ hipError_t launch_finalize_batch(int precision, const void* tab, uint32_t count,
                                  const int32_t* fin, hipStream_t s)
 {
     if (precision == 32)
-        finalize_batch_kernel<float><<<count, 1024, 0, s>>>(static_cast<const BatchEntry<float>*>(tab), T, fin);
+        finalize_batch_kernel<float><<<count, kThreads, 0, s>>>(static_cast<const BatchEntry<float>*>(tab), T, fin);
     else
-        finalize_batch_kernel<double><<<count, 1024, 0, s>>>(static_cast<const BatchEntry<double>*>(tab), T,
+        finalize_batch_kernel<double><<<count, kThreads, 0, s>>>(static_cast<const BatchEntry<double>*>(tab), T,
                                                                  fin);
     return hipGetLastError();
 }

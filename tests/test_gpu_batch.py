@@ -88,6 +88,34 @@ def test_batch_equals_single_runs(H, precision):
     B.close()
 
 
+def test_batch_many_record_groups_equals_single(H):
+    """A lattice whose passes write more than 1024 work-group records (96^3
+    with 256-site tiles and one-plane chunks: 1728, two groups of the
+    finalize's fold) ends bit for bit the same in a batch, whose finalize
+    sums the groups one after the other, as alone, where fold_groups_kernel
+    sums them in parallel."""
+    _say("batch vs single, two record groups")
+    shapes = [((96, 96, 96), 1, 1), ((16, 16, 16), 2, 4)]
+    T = [0.8, 1.1]
+    for precision in (64, 32):
+        alone = _make(H, precision, mix=shapes, seed0=90)
+        inb = _make(H, precision, mix=shapes, seed0=90)
+        B = H.Batch(inb)
+        for n, smp in [(2, False), (3, True), (1, False), (2, True)]:
+            B.sweep(T, n, sample=smp)
+            for g, t in zip(alone, T):
+                g.sweep(t, n, sample=smp)
+        for i, (a, b) in enumerate(zip(alone, inb)):
+            assert a.get_state() == b.get_state(), (precision, shapes[i])
+        for a, ob in zip(alone, B.observables()):
+            oa = a.observables()
+            oa.pop("status")
+            assert oa == ob, precision
+        B.close()
+        for g in alone + inb:
+            g.close()
+
+
 def test_per_lattice_sample_flags(H):
     """Lattices in different phases (some sampling, some not) in one batch
     equal the same lattices swept alone with their own flags."""

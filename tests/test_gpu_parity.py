@@ -121,6 +121,35 @@ def test_plain_method_16cubed_observables(H, O):
     _say("16^3: <|m|> =", a["mean_m"][0], " <E>/N =", a["mean_E"])
 
 
+def test_many_record_groups_fp64_observables(H, O):
+    """More than 1024 work-group records per pass: 96^3 FP64 with 256-site
+    tiles and one-plane chunks writes 1728 records, two groups of the
+    finalize's fold, whose sums fold_groups_kernel forms in parallel (the
+    on-demand measurement also writes 1728).  Spins within 1e-12 after
+    every sweep; the sampled means and the measured energies equal the
+    reference's."""
+    _say("96^3 fp64, two record groups")
+    shape = (96, 96, 96)
+    kw = dict(inputs.random_params(7), seed=4321, instance=2, theta0_deg=30)
+    S = inputs.random_unit_spins(96 ** 3, 5)
+    g, o = _pair(H, O, shape, kw, spins=S)
+    g.set_launch(1, 1)
+    T = 0.9
+
+    def step(s):
+        g.sweep(T, sample=True)
+        return o.sweep(T, sample=True)
+
+    _compare_every_sweep(g, o, 4, step, shape)
+    a, b = g.observables(), o.observables(T)
+    assert a["samples"] == b["samples"] == 4
+    for k in ("mean_m", "mean_E"):
+        assert np.allclose(a[k], b[k], rtol=1e-11, atol=1e-13), (k, a[k], b[k])
+    for k in ("E", "E_exch", "E_uni", "E_cub", "E_zee"):
+        assert abs(a[k] - b[k]) <= 1e-11 * max(1.0, abs(b[k])), k
+    assert np.allclose(a["M"], b["M"], rtol=0, atol=1e-9)
+
+
 CSHAPES = [(4, 4, 4), (8, 8, 8), (6, 10, 4), (16, 16, 16), (2, 2, 2), (12, 6, 2)]
 
 
