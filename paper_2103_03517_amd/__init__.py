@@ -225,6 +225,11 @@ class Lattice:
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if self.stream != torch.cuda.current_stream(self.device):
+            # the workspace was allocated on the current stream but is used on
+            # another: the caching allocator must not hand it out again before
+            # that stream's work on it has finished
+            self.workspace.record_stream(self.stream)
         h = ctypes.c_void_p()
         st = self._lib.hmc_init_lattice(ctypes.byref(self.params),
                                         ctypes.c_void_p(self.workspace.data_ptr()), nbytes,

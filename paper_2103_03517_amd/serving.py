@@ -185,8 +185,14 @@ class Server:
     `ahead` ticks ahead of the device."""
 
     def __init__(self, precision=32, hbm_budget=32 << 30, max_slots=64, quantum=50, shapes=None,
-                 graph=0, ahead=3, log=None):
+                 graph=0, ahead=3, solo_streams=4, log=None):
         self.precision = int(precision)
+        # jobs that run alone (constrained and film jobs) go round-robin onto
+        # this many streams of their own (default priority), so that their
+        # small launches overlap the batch's instead of queueing behind them
+        self.solo_streams = int(solo_streams)
+        self._streams = []
+        self._next_stream = 0
         self.hbm_budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.quantum = int(quantum)
@@ -229,8 +235,16 @@ class Server:
             self._grains[key] = m
         return self._grains[key], first
 
+    def _solo_stream(self):
+        if not self._streams:
+            return None
+        s = self._streams[self._next_stream % len(self._streams)]
+        self._next_stream += 1
+        return s
+
     def _admit(self, job, now):
-        job.lattice = Lattice(*job.shape, **job.lattice_kw(self.precision))
+        stream = None if job.batched else self._solo_stream()
+        job.lattice = Lattice(*job.shape, stream=stream, **job.lattice_kw(self.precision))
         if job.kind == "film":
             # enqueued without waiting; checked on the host the first time
             masks, first = self._film_masks(job)
@@ -308,6 +322,8 @@ class Server:
 
         done = []
         stream = torch.cuda.current_stream()
+        if self.solo_streams > 0 and not self._streams:
+            self._streams = [torch.cuda.Stream() for _ in range(self.solo_streams)]
 
         def consume(block):
             """Takes every snapshot that has reached the host (all of them,
@@ -315,8 +331,15 @@ class Server:
             read it was."""
             nonlocal used
             t_ph = time.perf_counter()
-            while inflight and (block or inflight[0][0].ready()):
-                snap, js, walls = inflight.popleft()
+            # snapshots of different streams finish out of order; a job's own
+            # snapshots share its stream, so they are taken in order
+            keep = collections.deque()
+            while inflight:
+                item = inflight.popleft()
+                if not (block or item[0].ready()):
+                    keep.append(item)
+                    continue
+                snap, js, walls = item
                 obs = snap.observables()
                 for j, o in zip(js, obs):
                     j.reads.append(o)
@@ -331,6 +354,7 @@ class Server:
                         used -= j.bytes
                         done.append(j)
                         draining.remove(j)
+            inflight.extend(keep)
             self.phase_s["read"] += time.perf_counter() - t_ph
 
         while pending or waiting or active or draining or inflight:
@@ -397,10 +421,14 @@ class Server:
                         host.copy_(row[:, 2], non_blocking=True)
                         copies.append((j, host))
                         j.prof_enqueued += 1
-                snap = Snapshot([j.lattice for j in hit], stream)
-                snap.event.record(stream)
-                inflight.append((snap, hit, [(j, h.numpy()) for j, h in copies]))
-                self.stats["snapshots"] += 1
+                # one snapshot per stream: the batch's and each solo stream's
+                groups = collections.OrderedDict()
+                for j in hit:
+                    groups.setdefault(j.lattice.stream, []).append(j)
+                for st_, js in groups.items():
+                    snap = Snapshot([j.lattice for j in js], st_)
+                    inflight.append((snap, js, [(j, h.numpy()) for j, h in copies if j in js]))
+                    self.stats["snapshots"] += 1
             self.phase_s["enqueue"] += time.perf_counter() - t_ph
             # jobs whose sweeps are all enqueued leave the batch; they finish
             # when their last snapshot arrives
@@ -410,12 +438,16 @@ class Server:
                 draining.extend(finished)
                 if any(j.batched for j in finished):
                     changed = True
-            ev = torch.cuda.Event()
-            ev.record(stream)
-            ticks.append(ev)
+            evs = []
+            for st_ in [stream] + self._streams:
+                ev = torch.cuda.Event()
+                ev.record(st_)
+                evs.append(ev)
+            ticks.append(evs)
             t_ph = time.perf_counter()
             while len(ticks) > self.ahead:
-                ticks.popleft().synchronize()
+                for ev in ticks.popleft():
+                    ev.synchronize()
             self.phase_s["wait"] += time.perf_counter() - t_ph
             consume(block=False)
             if finished and self.log:
