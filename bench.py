@@ -191,9 +191,11 @@ def batch_leg(sequential=False, tail=12000):
     from paper_2103_03517_amd import protocols as P
     jobs = P.c4_jobs(64)
     log(f"leg 5: batched m(T) jobs, {len(jobs)} lattices, FP32 (autotuned launch shapes)")
-    r32, i32 = P.batched_mt(jobs, 32, log=log, tail=tail)
+    # graph replay of each 200-sweep call (one capture per chunk and sample
+    # flag): 1-2 % faster than eager launches on this batch, same bits
+    r32, i32 = P.batched_mt(jobs, 32, log=log, tail=tail, graph=200)
     log("  the same jobs in FP64, independent keys")
-    r64, i64 = P.batched_mt(jobs, 64, tune=False, seed=5, log=log, tail=tail)
+    r64, i64 = P.batched_mt(jobs, 64, tune=False, seed=5, log=log, tail=tail, graph=200)
     cmp = P.compare_precisions(r32, r64)
     shapes = {}
     for (e, _), sh in zip(jobs, i32["shapes"]):
@@ -505,7 +507,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        log("cpu baseline: serial FP64 reference, 3 sampled sweeps at 256^3; then the whole host")
+        log("cpu baseline: serial FP64 reference, 7 sampled sweeps at 256^3; then the whole host")
         cpu = cpu_baseline(7)   # about 11 s of one host thread
         log(f"  {cpu['value'] / 1e6:.2f} M updates/s on one thread; {cpu['aggregate_value'] / 1e6:.2f} M "
             f"updates/s from {cpu['aggregate_processes']} processes ({cpu['cpu_model']}, nproc {cpu['nproc']})")

@@ -223,13 +223,12 @@ class Lattice:
             st = self._lib.hmc_init_lattice(ctypes.byref(self.params), None, 0, None, ctypes.byref(h))
             raise HmcError(st, self._lib.hmc_strerror(st).decode())
         self.device = torch.device(device)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        if self.stream != torch.cuda.current_stream(self.device):
-            # the workspace was allocated on the current stream but is used on
-            # another: the caching allocator must not hand it out again before
-            # that stream's work on it has finished
-            self.workspace.record_stream(self.stream)
+        # the workspace comes from the pool of the stream the lattice runs on:
+        # a block last used on another stream could still be in use by work
+        # pending there, and the caching allocator orders reuse per stream
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
         st = self._lib.hmc_init_lattice(ctypes.byref(self.params),
                                         ctypes.c_void_p(self.workspace.data_ptr()), nbytes,

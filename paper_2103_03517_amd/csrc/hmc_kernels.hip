@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kGroupThreads) void fold_groups_kernel(const double
                                                                     uint32_t npart, double* l2)
 {
     __shared__ double scratch[5 * kNumPart];
-    group_sum(part, stride, npart, blockIdx.x, scratch, scratch + 4 * kNumPart);
+    group_sums<kGroupThreads>(part, stride, npart, blockIdx.x, blockIdx.x + 1u, scratch, scratch + 4 * kNumPart);
     if (threadIdx.x < (uint32_t)kNumPart)
         l2[(size_t)blockIdx.x * kNumPart + threadIdx.x] = scratch[4 * kNumPart + threadIdx.x];
 }
@@ -692,7 +692,7 @@ hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t blac
     const uint32_t stride = (uint32_t)d.max_blocks;
     const uint32_t G = (uint32_t)cdiv((uint64_t)part_blocks, (uint64_t)kGroupRecords);
     const double* l2 = nullptr;
-    if ((fin & kFinObs) && G > 1) {
+    if ((fin & kFinObs) && G > kFinGroupsInKernel) {
         // the group sums, in parallel, into the space after the partial rows
         double* g2 = d.part + (size_t)kNumPart * stride;
         fold_groups_kernel<<<G, kGroupThreads, 0, s>>>(d.part, stride, (uint32_t)part_blocks, g2);

@@ -329,25 +329,38 @@ __device__ __forceinline__ void block_end(const KArgs<R>& a, int colour, uint32_
 // (from 0.0); wave_sum adds the threads of each wave and the four wave sums
 // are added in wave order (from 0.0), giving the group sum S_g.  The total is
 // ((0.0 + S_0) + S_1) + ... .  A group is one round of loads (48 per thread).
-// With more than one group the single-lattice path computes the group sums
-// in parallel (fold_groups_kernel, one work-group per group) and the
-// finalize adds them; the batch finalize computes them one after the other.
+// With more than one group the single-lattice path forms the group sums in
+// parallel (fold_groups_kernel, one work-group per group) and the finalize
+// adds them; the batch and constrained finalizes form them one after the
+// other (a 1024-thread work-group would form four per round).
 // The counts are integers, summed in any order.
 // ---------------------------------------------------------------------------
 constexpr int kGroupRecords = 1024;
 constexpr int kGroupThreads = 256;
-// doubles of shared memory finalize_body needs: the wave sums [4][kNumPart],
-// the totals [kNumPart + 1] and the per-wave counts [16]
-constexpr int kFinScratch = 4 * kNumPart + kNumPart + 1 + 16;
+// doubles of shared memory finalize_body needs: the wave sums [16][kNumPart],
+// the group sums of a round [4][kNumPart], the totals [kNumPart + 1] and the
+// per-wave counts [16]
+constexpr int kFinScratch = 16 * kNumPart + 4 * kNumPart + kNumPart + 1 + 16;
+// group sums the single-lattice finalize forms itself; above this,
+// fold_groups_kernel forms them in parallel first.  One work-group reading
+// several groups is bound by what one CU can fetch (measured on MI355X: 24
+// us for the 7 groups of a 384^3 pass with 8-plane chunks, against 13 us
+// with the parallel fold), so the finalize takes one group at most.
+constexpr uint32_t kFinGroupsInKernel = 1;
 
-// S_g of group g into sg[0..kNumPart) (shared memory).  Every thread of the
-// work-group calls it (it holds barriers); threads 0..255 do the work.
-__device__ __forceinline__ void group_sum(const double* part, uint32_t stride, uint32_t npart, uint32_t g,
-                                          double* wsum, double* sg)
+// The group sums S_g of groups g0, g0 + 1, ... (those below G), one group
+// per 256 threads of the work-group, into sg[j * kNumPart ..] for group
+// g0 + j (shared memory; wsum holds [NT / 64][kNumPart]).  Every thread of
+// the work-group calls it (it holds barriers).
+template <int NT>
+__device__ __forceinline__ void group_sums(const double* part, uint32_t stride, uint32_t npart, uint32_t g0,
+                                           uint32_t G, double* wsum, double* sg)
 {
-    const uint32_t t = threadIdx.x;
-    if (t < (uint32_t)kGroupThreads) {
-        const uint32_t r0 = g * (uint32_t)kGroupRecords + t;
+    constexpr int PG = NT / kGroupThreads;
+    const uint32_t t = threadIdx.x, tl = t % (uint32_t)kGroupThreads;
+    const uint32_t g = g0 + t / (uint32_t)kGroupThreads;
+    if (g < G) {                       // uniform over each 256 threads (whole waves)
+        const uint32_t r0 = g * (uint32_t)kGroupRecords + tl;
         double q[4][kNumPart];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -376,10 +389,14 @@ __device__ __forceinline__ void group_sum(const double* part, uint32_t stride, u
         }
     }
     __syncthreads();
-    if (t < (uint32_t)kNumPart) {
-        double x = 0.0;
-        for (int w = 0; w < kGroupThreads / 64; ++w) x += wsum[w * kNumPart + t];
-        sg[t] = x;
+    if (t < (uint32_t)(PG * kNumPart)) {
+        const uint32_t j = t / (uint32_t)kNumPart, e = t % (uint32_t)kNumPart;
+        if (g0 + j < G) {
+            double x = 0.0;
+            for (int w = 0; w < kGroupThreads / 64; ++w)
+                x += wsum[((int)j * (kGroupThreads / 64) + w) * kNumPart + (int)e];
+            sg[j * kNumPart + e] = x;
+        }
     }
     __syncthreads();
 }
@@ -396,8 +413,9 @@ __device__ __forceinline__ void finalize_body(DevState* st, const double* part, 
 {
     static_assert(NT >= kGroupThreads && NT % 64 == 0 && NT <= 1024, "work-group size");
     const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
-    double* wsum = scratch;                                                   // [4][kNumPart]
-    double* tot = scratch + 4 * kNumPart;                                     // [kNumPart + 1]
+    double* wsum = scratch;                                                   // [16][kNumPart]
+    double* sg = scratch + 16 * kNumPart;                                     // [4][kNumPart]
+    double* tot = sg + 4 * kNumPart;                                          // [kNumPart + 1]
     unsigned long long* wc = reinterpret_cast<unsigned long long*>(tot + kNumPart + 1);   // [NT / 64]
     // the last wave takes no part in the record fold: one of its threads
     // copies the chain state while the others fold
@@ -431,10 +449,13 @@ __device__ __forceinline__ void finalize_body(DevState* st, const double* part, 
                 tot[t] = x;
             }
         } else {
+            // rounds of NT / 256 groups formed side by side, added in order
+            constexpr uint32_t PG = NT / kGroupThreads;
             double run = 0.0;          // threads 0..kNumPart-1: the running total
-            for (uint32_t g = 0; g < G; ++g) {
-                group_sum(part, stride, npart, g, wsum, tot);
-                if (t < (uint32_t)kNumPart) run += tot[t];
+            for (uint32_t g0 = 0; g0 < G; g0 += PG) {
+                group_sums<NT>(part, stride, npart, g0, G, wsum, sg);
+                if (t < (uint32_t)kNumPart)
+                    for (uint32_t j = 0; j < PG && g0 + j < G; ++j) run += sg[j * kNumPart + t];
             }
             if (t < (uint32_t)kNumPart) tot[t] = run;
         }

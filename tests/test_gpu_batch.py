@@ -89,15 +89,17 @@ def test_batch_equals_single_runs(H, precision):
 
 
 def test_batch_many_record_groups_equals_single(H):
-    """A lattice whose passes write more than 1024 work-group records (96^3
-    with 256-site tiles and one-plane chunks: 1728, two groups of the
-    finalize's fold) ends bit for bit the same in a batch, whose finalize
-    sums the groups one after the other, as alone, where fold_groups_kernel
-    sums them in parallel."""
-    _say("batch vs single, two record groups")
-    shapes = [((96, 96, 96), 1, 1), ((16, 16, 16), 2, 4)]
-    T = [0.8, 1.1]
+    """Lattices whose passes write more than 1024 work-group records end bit
+    for bit the same in a batch, whose finalize forms the group sums one
+    after the other, as alone, where fold_groups_kernel forms them in
+    parallel: 96^3 with 256-site tiles and one-plane chunks writes 1728
+    records (two groups) and, in FP32, 256^3 likewise 32768 (32 groups)."""
+    _say("batch vs single, several record groups")
     for precision in (64, 32):
+        shapes = [((96, 96, 96), 1, 1), ((16, 16, 16), 2, 4)]
+        if precision == 32:
+            shapes.append(((256, 256, 256), 1, 1))
+        T = [0.8, 1.1, 1.3][:len(shapes)]
         alone = _make(H, precision, mix=shapes, seed0=90)
         inb = _make(H, precision, mix=shapes, seed0=90)
         B = H.Batch(inb)

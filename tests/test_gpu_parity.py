@@ -125,9 +125,8 @@ def test_many_record_groups_fp64_observables(H, O):
     """More than 1024 work-group records per pass: 96^3 FP64 with 256-site
     tiles and one-plane chunks writes 1728 records, two groups of the
     finalize's fold, whose sums fold_groups_kernel forms in parallel (the
-    on-demand measurement also writes 1728).  Spins within 1e-12 after
-    every sweep; the sampled means and the measured energies equal the
-    reference's."""
+    on-demand measurement also writes 1728).  Spins within 1e-12 after every sweep;
+    the sampled means and the measured energies equal the reference's."""
     _say("96^3 fp64, two record groups")
     shape = (96, 96, 96)
     kw = dict(inputs.random_params(7), seed=4321, instance=2, theta0_deg=30)
@@ -562,6 +561,12 @@ def test_full_size_fp64_one_sweep_matches_reference(H, O):
     assert ob["accepted_last"] == acc
     assert ob["theta_deg"] == o.counters()[0]
     assert np.max(np.abs(g.spins() - o.spins())) <= TOL
+    # the measurement writes 32768 work-group records: 32 groups, whose sums
+    # fold_groups_kernel forms in parallel before the finalize adds them
+    b = o.observables(0.8)
+    for k in ("E", "E_exch", "E_uni"):
+        assert abs(ob[k] - b[k]) <= 1e-11 * max(1.0, abs(b[k])), (k, ob[k], b[k])
+    assert np.allclose(ob["M"], b["M"], rtol=0, atol=1e-7), (ob["M"], b["M"])
 
 
 def test_paper_size_fp32_marches_agree(H):

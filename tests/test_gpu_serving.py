@@ -38,6 +38,31 @@ def _mix(S, seed=5):
             S.Job(0, 0.8, instance=7, arrival=0.02, kind="film", shape=(24, 16, 3), diameter=5.0, **kw)]
 
 
+def test_lattice_on_another_stream_takes_that_streams_memory(S):
+    """A lattice on a stream other than torch's current one allocates its
+    workspace from that stream's pool: a block just freed on the current
+    stream (whose queued work may still use it) is not handed to it.  Its
+    spins then equal those of the same lattice made on the current stream."""
+    import torch
+    import paper_2103_03517_amd as H
+    kw = dict(precision=64, J=1.0, Ku=0.02, seed=3, init="random")
+    nbytes = H.workspace_bytes(H.make_params(24, 16, 12, **kw))
+    ref = H.Lattice(24, 16, 12, **kw)
+    ref.sweep(0.7, 5)
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    x.fill_(0xAB)                        # work queued on the current stream
+    freed = x.data_ptr()
+    del x
+    side = torch.cuda.Stream()
+    g = H.Lattice(24, 16, 12, stream=side, **kw)
+    assert g.workspace.data_ptr() != freed
+    g.sweep(0.7, 5)
+    torch.cuda.synchronize()
+    assert np.array_equal(g.spins(), ref.spins())
+    g.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("precision", [32, 64])
 def test_result_same_alone_and_in_mix(S, precision):
     shapes = {(16,) * 3: (1, 4), (24,) * 3: (2, 8), (32,) * 3: (1, 16)}

@@ -1,8 +1,8 @@
 """hmc_measure_static (the measurement without a workspace, its reduction
 scratch in the library's static device array) against hmc_observables on the
-same spins: the same kernels with the same grid, so the same bits.  Three
-calls in a row, each on a smaller lattice than the last (the first with more
-than 1024 work-group records), then a call
+same spins: the same kernels with the same grid, so the same bits.  Four
+calls in a row, each on a smaller lattice than the last (the first two with
+more than 1024 work-group records), then a call
 on spins holding a non-finite value (reported) followed by a clean call (the
 sticky flag is cleared between calls)."""
 import numpy as np
@@ -29,9 +29,11 @@ def _model(seed):
 
 def test_measure_static_matches_observables(H):
     import sys
-    # 96^3: 1728 measurement records, two groups of the finalize's fold (the
-    # group sums in the static array too); each call smaller than the last
-    cases = [((96, 96, 96), 32, "periodic"), ((64, 48, 40), 64, "periodic"), ((16, 12, 10), 32, "antiperiodic")]
+    # 256^3: 32768 measurement records, 32 groups of the finalize's fold,
+    # 96^3: 1728 records, two groups; their sums are formed in parallel into
+    # the static array; each call smaller than the last
+    cases = [((256, 256, 256), 32, "periodic"), ((96, 96, 96), 32, "periodic"), ((64, 48, 40), 64, "periodic"),
+             ((16, 12, 10), 32, "antiperiodic")]
     for shape, precision, bz in cases:
         print("measure_static", shape, precision, bz, file=sys.stderr, flush=True)
         g = H.Lattice(*shape, precision=precision, boundary_z=bz, **_model(sum(shape)))
