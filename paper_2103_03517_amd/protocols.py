@@ -607,6 +607,7 @@ def main(argv=None):
     w = sub.add_parser("stiffness", help="domain-wall widths -> exchange stiffness A(T)")
     w.add_argument("--nz", type=int, default=512)
     w.add_argument("--cross", type=int, default=64)
+    w.add_argument("--Ku", type=float, default=0.01)
     f = sub.add_parser("film", help="granular film m(T) and the multi-Bloch fit")
     f.add_argument("--n", type=int, default=512)
     f.add_argument("--nz", type=int, default=5)
@@ -650,7 +651,7 @@ def main(argv=None):
         res = film_mt(temps, shape=(args.n, args.n, args.nz), diameter=args.diameter,
                       grains=not args.continuous, log=log)
     elif args.cmd == "stiffness":
-        res = stiffness_run(shape=(args.cross, args.cross, args.nz), log=log)
+        res = stiffness_run(shape=(args.cross, args.cross, args.nz), Ku=args.Ku, log=log)
     elif args.cmd == "films":
         res = film_grid(n=args.n, thicknesses=args.nz, diameters=args.diameters, log=log)
     elif args.cmd == "eq4":
