@@ -462,10 +462,16 @@ def wall_run(temps, shape=(64, 64, 512), precision=32, J=1.0, Ku=0.01, equil=500
     B = Batch(lats)
     B.sweep(list(temps), equil)
     fits = [[] for _ in temps]
+    # also the plain average of the profiles (the wall is free to wander
+    # along z, so this average is wider than the snapshots)
+    psum = [np.zeros(nz) for _ in temps]
+    nprof = 0
     for _ in range(max(samples // every, 1)):
         B.sweep(list(temps), every, sample=True)
+        nprof += 1
         for i, g in enumerate(lats):
             prof = g.plane_means()[:, 2]
+            psum[i] += prof
             try:
                 fits[i].append(Wm.fit_wall(prof, delta_guess=Wm.zero_temperature_width(J, Ku)))
             except RuntimeError:
@@ -478,9 +484,16 @@ def wall_run(temps, shape=(64, 64, 512), precision=32, J=1.0, Ku=0.01, equil=500
         if len(f):
             r.update(m_wall=float(f[:, 0].mean()), delta=float(f[:, 2].mean()),
                      se_delta=float(f[:, 2].std(ddof=1) / math.sqrt(len(f))) if len(f) > 1 else float("nan"))
+            try:
+                r["delta_mean_profile"] = Wm.fit_wall(psum[i] / nprof,
+                                                      delta_guess=Wm.zero_temperature_width(J, Ku))[2]
+            except RuntimeError:
+                pass
             if K_of_T is not None and T in K_of_T:
                 r["K"] = K_of_T[T]
                 r["A"] = Wm.exchange_stiffness(K_of_T[T], r["delta"])
+                if "delta_mean_profile" in r:
+                    r["A_mean_profile"] = Wm.exchange_stiffness(K_of_T[T], r["delta_mean_profile"])
         out.append(r)
         if log:
             log(f"T={T:.3f} wall fits {r['fits']}: Delta={r.get('delta', float('nan')):.3f} "
@@ -508,8 +521,13 @@ def stiffness_run(temps=(0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 
     res = {"rows": rows, "A0": J / 2.0}
     if len(low) >= 2:
         res["k"] = A.callen_callen_exponent([r["A"] for r in low], J / 2.0, [r["m"] for r in low])
+    lowp = [r for r in low if r.get("A_mean_profile", 0) > 0]
+    if len(lowp) >= 2:
+        # the same from the width of the time-averaged profile
+        res["k_mean_profile"] = A.callen_callen_exponent([r["A_mean_profile"] for r in lowp], J / 2.0,
+                                                         [r["m"] for r in lowp])
     if log:
-        log(f"A(T) ~ m^k: k = {res.get('k')}")
+        log(f"A(T) ~ m^k: k = {res.get('k')} (width of the time-averaged profile: {res.get('k_mean_profile')})")
     return res
 
 
