@@ -45,3 +45,38 @@ def random_bond_masks(shape, p_cut, seed):
         nb_cut = np.roll(cut, 1, axis=axis)               # the same bond seen from the + neighbour
         mask[nb_cut] &= np.uint8(~(1 << lo) & 0xFF)
     return mask.reshape(-1)
+
+
+def grain_bond_masks(shape, diameter, seed):
+    """Bond masks of a granular film: columnar grains from the nearest of
+    nx*ny/(pi d^2/4) seeds placed uniformly in the periodic plane, every
+    in-plane bond between two grains cut at both ends (z bonds stay).
+    Returns (masks in site order, number of grains)."""
+    from scipy.spatial import cKDTree
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    ng = max(1, int(round(nx * ny / (np.pi * diameter ** 2 / 4.0))))
+    seeds = rng.uniform(0.0, 1.0, size=(ng, 2)) * np.array([nx, ny])
+    yy, xx = np.meshgrid(np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    _, grain = cKDTree(seeds, boxsize=[nx, ny]).query(np.stack([xx.ravel(), yy.ravel()], axis=1))
+    grain = grain.reshape(ny, nx)
+    plane = np.full((ny, nx), 0x3F, dtype=np.uint8)
+    cut_x = grain != np.roll(grain, -1, axis=1)          # bond to the x+ neighbour
+    plane[cut_x] &= np.uint8(~(1 << 1) & 0xFF)
+    plane[np.roll(cut_x, 1, axis=1)] &= np.uint8(~(1 << 0) & 0xFF)
+    cut_y = grain != np.roll(grain, -1, axis=0)          # bond to the y+ neighbour
+    plane[cut_y] &= np.uint8(~(1 << 3) & 0xFF)
+    plane[np.roll(cut_y, 1, axis=0)] &= np.uint8(~(1 << 2) & 0xFF)
+    return np.broadcast_to(plane, (nz, ny, nx)).reshape(-1).copy(), len(np.unique(grain))
+
+
+def wall_spins(shape, width, seed, noise=0.05):
+    """A wall across z: S = (sech u, 0, tanh u) with u = pi (z - nz/2)/width,
+    plus seeded noise, normalised; site order x fastest."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    u = np.pi * (np.arange(nz) + 0.5 - nz / 2.0) / width
+    prof = np.stack([1.0 / np.cosh(u), np.zeros(nz), np.tanh(u)], axis=1)
+    v = np.repeat(prof, nx * ny, axis=0) + noise * rng.normal(size=(nx * ny * nz, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return v

@@ -569,6 +569,56 @@ def test_full_size_fp64_one_sweep_matches_reference(H, O):
     assert np.allclose(ob["M"], b["M"], rtol=0, atol=1e-7), (ob["M"], b["M"])
 
 
+def test_full_size_film_fp64_matches_reference(H, O):
+    """The film workload at its largest size: 1024 x 1024 x 15 (15.7 M spins),
+    open z, columnar Voronoi grains of mean diameter 16 with every intergrain
+    bond cut, Ku = 0.01 along z, FP64, from the same random spins: two
+    sampled sweeps match the reference spin by spin within 1e-12, with the
+    same acceptance counts and cone angle, and the same energies."""
+    shape = (1024, 1024, 15)
+    mask, ng = inputs.grain_bond_masks(shape, 16.0, 11)
+    _say("film 1024x1024x15 fp64,", ng, "grains")
+    kw = dict(J=1.0, Ku=0.01, eu=(0, 0, 1), seed=21, instance=1, boundary_z="open")
+    S = inputs.random_unit_spins(shape[0] * shape[1] * shape[2], 13)
+    g = H.Lattice(*shape, precision=64, bond_masks=True, **kw)
+    o = O.OracleLattice(*shape, init=None, **kw)
+    g.set_bond_masks(mask)
+    o.set_bond_masks(mask)
+    g.set_spins(S)
+    o.set_spins(S)
+    T = 0.9
+    for s in range(2):
+        g.sweep(T, sample=True)
+        acc = o.sweep(T, sample=True)
+        ob = g.observables()
+        assert ob["accepted_last"] == acc, s
+        assert ob["theta_deg"] == o.counters()[0], s
+        assert np.max(np.abs(g.spins() - o.spins())) <= TOL, s
+    a, b = g.observables(), o.observables(T)
+    for k in ("E", "E_exch", "E_uni"):
+        assert abs(a[k] - b[k]) <= 1e-11 * max(1.0, abs(b[k])), (k, a[k], b[k])
+    g.close()
+
+
+def test_full_size_wall_fp64_matches_reference(H, O):
+    """The wall workload at its size: 64 x 64 x 512, anti-periodic along z,
+    from the same noisy wall across z, Ku = 0.01, FP64: three sampled sweeps
+    match the reference spin by spin within 1e-12."""
+    _say("wall 64x64x512 fp64")
+    shape = (64, 64, 512)
+    kw = dict(J=1.0, Ku=0.01, eu=(0, 0, 1), seed=6, instance=4, boundary_z="antiperiodic")
+    S = inputs.wall_spins(shape, 22.2, 17)
+    g, o = _pair(H, O, shape, kw, spins=S)
+    T = 0.5
+
+    def step(s):
+        g.sweep(T, sample=True)
+        return o.sweep(T, sample=True)
+
+    _compare_every_sweep(g, o, 3, step, shape)
+    g.close()
+
+
 def test_paper_size_fp32_marches_agree(H):
     """464^3 FP32 (99.9 M spins, the lattice size of the paper's timing and of
     the bench leg, which runs the two-plane march): two sampled sweeps give
