@@ -122,7 +122,9 @@ typedef struct {
 /* Per-kernel timing collected with HIP events on the handle's stream while
  * timing is enabled.  Kinds: 0 = standard colour pass, 1 = constrained pair
  * pass, 2 = reductions (the per-sweep finalize: cone angle, counters,
- * accumulators; and the measurement of the current spins), 3 = the rest:
+ * accumulators, with the parallel fold of the work-group records that comes
+ * before it on large lattices; and the measurement of the current spins),
+ * 3 = the rest:
  * initialisation, the copies in and out of a constrained call, and its
  * neighbour-sum stencils (between sweeps launched together with the
  * finalize). */
