@@ -622,6 +622,7 @@ def main(argv=None):
     an.add_argument("--size", type=int, default=128)
     an.add_argument("--sweeps", type=int, default=3000)
     an.add_argument("--equil", type=int, default=1000)
+    an.add_argument("--Kc", type=float, default=0.05)
     w = sub.add_parser("stiffness", help="domain-wall widths -> exchange stiffness A(T)")
     w.add_argument("--nz", type=int, default=512)
     w.add_argument("--cross", type=int, default=64)
@@ -680,7 +681,7 @@ def main(argv=None):
     elif args.cmd == "eq4conv":
         res = eq4_convergence(Kcs=args.Kc, temps=args.temps, size=args.size, log=log)
     elif args.cmd == "anisotropy":
-        res = anisotropy_run(size=args.size, sweeps=args.sweeps, equil=args.equil, log=log)
+        res = anisotropy_run(size=args.size, sweeps=args.sweeps, equil=args.equil, Kc=args.Kc, log=log)
     elif args.cmd == "batched":
         jobs = c4_jobs(args.count)
         r32, i32 = batched_mt(jobs, 32, args.equil, args.samples, args.block, log=log)
