@@ -195,6 +195,8 @@ def batch_leg(sequential=False, tail=12000):
     # flag): 1-2 % faster than eager launches on this batch, same bits
     r32, i32 = P.batched_mt(jobs, 32, log=log, tail=tail, graph=200)
     log("  the same jobs in FP64, independent keys")
+    # (the autotuner's shapes and chunks gave the FP64 batch nothing: 5.50 s
+    # against 5.36 s untuned)
     r64, i64 = P.batched_mt(jobs, 64, tune=False, seed=5, log=log, tail=tail, graph=200)
     cmp = P.compare_precisions(r32, r64)
     shapes = {}
