@@ -169,11 +169,17 @@ def test_batch_fp64_matches_reference(H):
     _say("batch fp64 vs reference: worst", worst)
 
 
-def test_graph_replay_equals_eager(H):
+@pytest.mark.parametrize("chunk", [0, 20000])
+def test_graph_replay_equals_eager(H, chunk):
+    """Graph replay of every call gives the eager states, also when the batch
+    is swept in chunks (one graph per chunk and sample flag), as the bench's
+    batch leg runs it."""
     T = _temps(len(MIX), seed=5)
     eager = _make(H, 32, seed0=80)
     graph = _make(H, 32, seed0=80)
     Be, Bg = H.Batch(eager), H.Batch(graph)
+    Be.set_chunk_bytes(chunk)
+    Bg.set_chunk_bytes(chunk)
     Bg.set_graph(3)
     for rep, (n, smp) in enumerate([(7, False), (6, True), (3, True), (5, False)]):
         Be.sweep(T, n, sample=smp)
