@@ -571,9 +571,10 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": "pair_kernel<float> (one colour's pair moves, 128^3)",
                 "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(pair_ms, 5),
-                "note": "the 2 M-spin working set sits in the Infinity Cache; the pass is bound by its "
-                        "instruction issue (about 2600 VALU instructions per wave, waiting on memory 12-13 % of "
-                        "the time) and one random line per partner record, not by HBM bandwidth"}
+                "note": "the 2 M-spin working set sits in the Infinity Cache; the pass is bound by latency "
+                        "(each wave takes its pairs in dependent rounds: scan barriers, one random line per "
+                        "partner record, a long arithmetic chain; VALU busy about 45 % of the pass, waiting on "
+                        "memory 12-13 % of the time), not by HBM bandwidth or instruction issue"}
     line["kernel_timing"] = ("per-kernel averages from HIP events recorded by the library on the "
                              f"lattice's stream over a second region of {main_leg['kernel_timing_steps']} "
                              "steps of the same workload")
