@@ -212,6 +212,19 @@ __device__ __forceinline__ Vec4<R> v4(const V3<R>& v)
 #ifndef HMC_PAIR_BLOCKS
 #define HMC_PAIR_BLOCKS 512      // most work-groups of the pair pass
 #endif
+#ifndef HMC_PAIR_TILE_BLOCKS
+#define HMC_PAIR_TILE_BLOCKS 2   // blocks of 256 colour indices per pair-pass tile
+#endif
+constexpr uint32_t kPairTile = HMC_PAIR_TILE_BLOCKS * kThreads;
+
+// the smallest power of two >= n
+constexpr uint32_t ring_size(uint32_t n)
+{
+    uint32_t r = 1;
+    while (r < n) r *= 2;
+    return r;
+}
+
 #ifndef HMC_NB_BLOCKS
 #define HMC_NB_BLOCKS 2048       // most work-groups of the record stencil
 #endif
@@ -396,13 +409,15 @@ __device__ __forceinline__ void pair_move(const PairCtx<R>& x, Vec4<R>* own, uin
 // Pair pass of colour C.  The shuffled order pi of the colour indices is a
 // keyed bijection evaluated inline (nothing is stored); pair k is
 // (pi(2k), pi(2k+1)) (N_c is even: nx and ny are).  A work-group scans tiles
-// of 2 x 256 consecutive colour indices a; a is the first spin of pair
-// pi^-1(a)/2 when pi^-1(a) is even, and such pairs are queued in LDS in scan
-// order (wave ballots, waves in order), so the queue never depends on
-// scheduling.  The queue is drained in rounds of 256 pairs, one per thread,
-// and what is left of it carries over to the next tile: every lane runs a
-// pair move, and the first record of each pair is read near site order (only
-// the partner's is a random gather).  M_L is the moment along eC at the
+// of kPairTile consecutive colour indices a (blocks of 256); a is the first
+// spin of pair pi^-1(a)/2 when pi^-1(a) is even, and such pairs are queued in
+// LDS in scan order (blocks in order, wave ballots, waves in order), so the
+// queue never depends on scheduling; a tile takes one ballot round, two
+// barriers, for all of its blocks.
+// The queue is a ring in LDS drained in rounds of 256 pairs, one per thread,
+// and what is left of it stays for the next tile: every lane runs a pair
+// move, and the first record of each pair is read near site order (only the
+// partner's is a random gather).  M_L is the moment along eC at the
 // start of the sweep (one value for both colours, as in the paper).  OBS adds
 // the one-site terms of both final spins of every pair; since pi is a
 // bijection every site is covered once, and in the black pass every bond once
@@ -413,12 +428,14 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R
                                                         const V3<R> ec, const Shuffle f, const R scale,
                                                         const uint32_t part_base)
 {
-    constexpr uint32_t kTrip = 2 * kThreads;                 // indices scanned per tile
-    constexpr uint32_t kQueue = kTrip + kThreads;            // at most 255 carried + 512 new
+    constexpr uint32_t kU = kPairTile / kThreads;            // indices per thread and tile
+    constexpr uint32_t kTrip = kPairTile;                    // indices scanned per tile
+    constexpr uint32_t kRing = ring_size(kThreads - 1 + kTrip);  // queue ring: 255 left + kTrip new
+    static_assert((kRing & (kRing - 1)) == 0 && kRing >= kThreads - 1 + kTrip, "queue ring too small");
     constexpr int kWaves = kThreads / 64;
     __shared__ double scratch[5 * kNumPart];
-    __shared__ uint32_t qa[kQueue], qj[kQueue], qk[kQueue];
-    __shared__ uint32_t wcnt[kWaves];
+    __shared__ uint32_t qa[kRing], qj[kRing], qk[kRing];
+    __shared__ uint32_t wcnt[kU][kWaves];
     Vec4<R>* own = aos + (size_t)C * a.Nc;
     PairCtx<R> x;
     x.m = a.m;
@@ -441,63 +458,62 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const KArgs<R> a, Vec4<R
     Acc acc;
     Part<R> part;                                            // FP32 spins: the thread's sums, then FP64
     auto& pa = site_acc<R>(acc, part);
-    uint32_t held = 0;                                       // queued pairs, the same in every thread
+    // pairs queued and pairs taken so far, the same in every thread; the
+    // queue holds entries head .. tail - 1 at their positions modulo kRing
+    uint32_t head = 0, tail = 0;
     for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        uint32_t ia[kU], ja[kU], k[kU];
+        bool first[kU];
+        uint64_t ball[kU];
 #pragma unroll
-        for (uint32_t u = 0; u < kTrip / kThreads; ++u) {
-            const uint32_t ia = tile * kTrip + u * kThreads + t;
-            bool first = false;
-            uint32_t ja = 0, k = 0;
-            if (ia < a.Nc) {
-                const uint32_t pos = unshuffle_index(ia, a.Nc, f.half, f.mask, key);
-                first = (pos & 1u) == 0u;
-                if (first) {
-                    ja = shuffle_index(pos + 1u, a.Nc, f.half, f.mask, key);
-                    k = pos >> 1;
+        for (uint32_t u = 0; u < kU; ++u) {
+            ia[u] = tile * kTrip + u * kThreads + t;
+            first[u] = false;
+            ja[u] = 0;
+            k[u] = 0;
+            if (ia[u] < a.Nc) {
+                const uint32_t pos = unshuffle_index(ia[u], a.Nc, f.half, f.mask, key);
+                first[u] = (pos & 1u) == 0u;
+                if (first[u]) {
+                    ja[u] = shuffle_index(pos + 1u, a.Nc, f.half, f.mask, key);
+                    k[u] = pos >> 1;
                 }
             }
-            const uint64_t ball = __ballot(first);
-            if (lane == 0) wcnt[wave] = (uint32_t)__popcll(ball);
-            __syncthreads();
-            uint32_t off = held, total = held;
+            ball[u] = __ballot(first[u]);
+            if (lane == 0) wcnt[u][wave] = (uint32_t)__popcll(ball[u]);
+        }
+        // every wave has left the previous tile's queue reads: the slots past
+        // tail are free
+        __syncthreads();
+        // appended in scan order: index block u = 0 (waves in order), then u = 1
+#pragma unroll
+        for (uint32_t u = 0; u < kU; ++u) {
+            uint32_t off = tail, total = tail;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
-                off += (uint32_t)w < wave ? wcnt[w] : 0u;
-                total += wcnt[w];
+                off += (uint32_t)w < wave ? wcnt[u][w] : 0u;
+                total += wcnt[u][w];
             }
-            if (first) {
-                const uint32_t e = off + (uint32_t)__popcll(ball & below);
-                qa[e] = ia;
-                qj[e] = ja;
-                qk[e] = k;
+            if (first[u]) {
+                const uint32_t e = (off + (uint32_t)__popcll(ball[u] & below)) & (kRing - 1u);
+                qa[e] = ia[u];
+                qj[e] = ja[u];
+                qk[e] = k[u];
             }
-            held = total;
-            __syncthreads();
-        }
-        uint32_t done = 0;
-        for (; held - done >= kThreads; done += kThreads) {
-            const uint32_t e = done + t;
-            const uint32_t ia = qa[e], ja = qj[e];
-            pair_move<R, C, OBS>(x, own, qk[e], ia, ja, rec[ia], rec[ja], nacc, pa);
-        }
-        // the rest of the queue (fewer than 256 pairs) to its front
-        const uint32_t rest = held - done;
-        uint32_t ca = 0, cj = 0, ck = 0;
-        if (t < rest) {
-            ca = qa[done + t];
-            cj = qj[done + t];
-            ck = qk[done + t];
+            tail = total;
         }
         __syncthreads();
-        if (t < rest) {
-            qa[t] = ca;
-            qj[t] = cj;
-            qk[t] = ck;
+        for (; tail - head >= kThreads; head += kThreads) {
+            const uint32_t e = (head + t) & (kRing - 1u);
+            const uint32_t i = qa[e], j = qj[e];
+            pair_move<R, C, OBS>(x, own, qk[e], i, j, rec[i], rec[j], nacc, pa);
         }
-        held = rest;
-        __syncthreads();
     }
-    if (t < held) pair_move<R, C, OBS>(x, own, qk[t], qa[t], qj[t], rec[qa[t]], rec[qj[t]], nacc, pa);
+    if (t < tail - head) {
+        const uint32_t e = (head + t) & (kRing - 1u);
+        const uint32_t i = qa[e], j = qj[e];
+        pair_move<R, C, OBS>(x, own, qk[e], i, j, rec[i], rec[j], nacc, pa);
+    }
     if constexpr (OBS) flush_part(acc, pa);
     KArgs<R> ra = a;
     ra.part = a.part + part_base;
@@ -623,7 +639,7 @@ static void constrained_go(const DevLattice& d, int step, const double eC[3], do
     Rec<R>* rec = reinterpret_cast<Rec<R>*>(aos + 2 * (size_t)d.Nc);
     const uint32_t n = (uint32_t)d.Nc;
     const uint32_t full = cdiv(n, kThreads);
-    const uint32_t tiles = cdiv(n, 2u * kThreads);
+    const uint32_t tiles = cdiv(n, kPairTile);
     const uint32_t pgrid = tiles < (uint32_t)HMC_PAIR_BLOCKS ? tiles : (uint32_t)HMC_PAIR_BLOCKS;
     const uint32_t ngrid = full < (uint32_t)HMC_NB_BLOCKS ? full : (uint32_t)HMC_NB_BLOCKS;
     *blocks = pgrid;
