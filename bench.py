@@ -573,10 +573,9 @@ def main():
                 "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(pair_ms, 5),
                 "note": "the 2 M-spin working set sits in the Infinity Cache; the pass is bound neither by "
                         "HBM bandwidth nor by instruction issue (VALU busy about 45 % of the pass, waiting on "
-                        "memory 12-13 % of the time; a quarter fewer instructions, interleaved pair chains or "
-                        "more waves did not make it faster); its random partner line and its write-backs "
-                        "cost about 2.4 us each, and the rest is most likely the latency of its rounds of "
-                        "scan barriers"}
+                        "memory 12-13 % of the time; a quarter fewer instructions, interleaved pair chains, "
+                        "more waves or no work-group barriers did not make it faster); its random partner "
+                        "line and its write-backs cost about 2.4 us each"}
     line["kernel_timing"] = ("per-kernel averages from HIP events recorded by the library on the "
                              f"lattice's stream over a second region of {main_leg['kernel_timing_steps']} "
                              "steps of the same workload")
