@@ -23,6 +23,12 @@ enum PartSlot {
     kEexch, kEuni, kEcub, kEzee, // energy terms, each bond once
     kTx, kTy, kTz,              // anisotropy torque
 };
+// Rows a launch writes and the finalize folds: the moment and the energies,
+// plus the torque where it is measured (constrained sweeps and measurements).
+// The acceptance counts go to their own integer rows; the part rows past
+// these hold nothing.
+constexpr int kObsRows = 7;
+constexpr int kTorqueRows = 10;
 
 // What the finalize kernel folds into the chain state.
 enum FinFlags {

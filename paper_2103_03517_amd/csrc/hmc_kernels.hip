@@ -38,14 +38,18 @@ void finalize_kernel(DevState* st, const double* part, uint32_t stride, const ui
 }
 
 // Work-group g: the sum S_g of record group g (the order of finalize_body),
-// stored at l2[g * kNumPart ..].
+// its first nrows components stored at l2[g * kNumPart ..].
 __global__ __launch_bounds__(kGroupThreads) void fold_groups_kernel(const double* part, uint32_t stride,
-                                                                    uint32_t npart, double* l2)
+                                                                    uint32_t npart, uint32_t nrows, double* l2)
 {
     __shared__ double scratch[5 * kNumPart];
-    group_sums<kGroupThreads>(part, stride, npart, blockIdx.x, blockIdx.x + 1u, scratch, scratch + 4 * kNumPart);
-    if (threadIdx.x < (uint32_t)kNumPart)
-        l2[(size_t)blockIdx.x * kNumPart + threadIdx.x] = scratch[4 * kNumPart + threadIdx.x];
+    if (nrows == (uint32_t)kTorqueRows)
+        group_sums<kGroupThreads, kTorqueRows>(part, stride, npart, blockIdx.x, blockIdx.x + 1u, scratch,
+                                               scratch + 4 * kNumPart);
+    else
+        group_sums<kGroupThreads, kObsRows>(part, stride, npart, blockIdx.x, blockIdx.x + 1u, scratch,
+                                            scratch + 4 * kNumPart);
+    if (threadIdx.x < nrows) l2[(size_t)blockIdx.x * kNumPart + threadIdx.x] = scratch[4 * kNumPart + threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -711,7 +715,8 @@ hipError_t launch_finalize(const DevLattice& d, int64_t red_blocks, int64_t blac
     if ((fin & kFinObs) && G > kFinGroupsInKernel) {
         // the group sums, in parallel, into the space after the partial rows
         double* g2 = d.part + (size_t)kNumPart * stride;
-        fold_groups_kernel<<<G, kGroupThreads, 0, s>>>(d.part, stride, (uint32_t)part_blocks, g2);
+        const uint32_t nrows = (fin & kFinTorque) ? (uint32_t)kTorqueRows : (uint32_t)kObsRows;
+        fold_groups_kernel<<<G, kGroupThreads, 0, s>>>(d.part, stride, (uint32_t)part_blocks, nrows, g2);
         l2 = g2;
     }
     finalize_kernel<<<1, 1024, 0, s>>>(d.st, d.part, stride, d.cnt, (uint32_t)red_blocks, (uint32_t)black_blocks,

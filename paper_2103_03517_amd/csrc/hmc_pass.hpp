@@ -290,18 +290,40 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch)
 
 // The end of a producing launch: work-group b writes its acceptance count
 // and (OBS) its partial sums, component e at part[e * cnt_stride + b] (one
-// row per component, so the finalize reads each row coalesced).  They are reduced by finalize_kernel, launched
-// next on the same stream (the kernel boundary makes them visible).
-template <typename R, bool OBS>
+// row per component, so the finalize reads each row coalesced): the moment
+// and the energies, and with TQ the torque.  They are reduced by
+// finalize_kernel, launched next on the same stream (the kernel boundary
+// makes them visible).  scratch: at least 5 * kTorqueRows + 2 doubles.
+template <typename R, bool OBS, bool TQ = true>
 __device__ __forceinline__ void block_end(const KArgs<R>& a, int colour, uint32_t b, uint32_t nacc, const Acc& acc,
                                           double* scratch)
 {
     if (OBS) {
-        double v[kNumPart] = {acc.M[0], acc.M[1], acc.M[2], acc.ex, acc.eu, acc.ec, acc.ez,
-                              acc.tq[0], acc.tq[1], acc.tq[2], (double)nacc, 0.0};
-        block_sum<kNumPart>(v, scratch);
-        if (threadIdx.x < kNumPart) a.part[(size_t)threadIdx.x * a.cnt_stride + b] = scratch[threadIdx.x];
-        if (threadIdx.x == 0) a.cnt[(size_t)colour * a.cnt_stride + b] = (uint32_t)scratch[10];
+        constexpr int NV = TQ ? kTorqueRows : kObsRows;
+        double v[NV];
+        v[kMx] = acc.M[0];
+        v[kMy] = acc.M[1];
+        v[kMz] = acc.M[2];
+        v[kEexch] = acc.ex;
+        v[kEuni] = acc.eu;
+        v[kEcub] = acc.ec;
+        v[kEzee] = acc.ez;
+        if constexpr (TQ) {
+            v[kTx] = acc.tq[0];
+            v[kTy] = acc.tq[1];
+            v[kTz] = acc.tq[2];
+        }
+        // the count as an integer, its wave sums published by block_sum's barriers
+        uint32_t* s32 = reinterpret_cast<uint32_t*>(scratch + 5 * NV);
+        const uint32_t c = wave_sum(nacc);
+        if ((threadIdx.x & 63) == 0) s32[threadIdx.x >> 6] = c;
+        block_sum<NV>(v, scratch);
+        if (threadIdx.x < (uint32_t)NV) a.part[(size_t)threadIdx.x * a.cnt_stride + b] = scratch[threadIdx.x];
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < kThreads / 64; ++w) tot += s32[w];
+            a.cnt[(size_t)colour * a.cnt_stride + b] = tot;
+        }
     } else {
         uint32_t c = wave_sum(nacc);
         __syncthreads();
@@ -328,7 +350,8 @@ __device__ __forceinline__ void block_end(const KArgs<R>& a, int colour, uint32_
 // thread t of 256 adds records 1024g + t, + 256, + 512 and + 768 in turn
 // (from 0.0); wave_sum adds the threads of each wave and the four wave sums
 // are added in wave order (from 0.0), giving the group sum S_g.  The total is
-// ((0.0 + S_0) + S_1) + ... .  A group is one round of loads (48 per thread).
+// ((0.0 + S_0) + S_1) + ... .  A group is one round of loads (4 per folded row
+// and thread: the 7 rows of M and the energies, 10 with the torque).
 // With more than one group the single-lattice path forms the group sums in
 // parallel (fold_groups_kernel, one work-group per group) and the finalize
 // adds them; the batch and constrained finalizes form them one after the
@@ -352,7 +375,7 @@ constexpr uint32_t kFinGroupsInKernel = 1;
 // per 256 threads of the work-group, into sg[j * kNumPart ..] for group
 // g0 + j (shared memory; wsum holds [NT / 64][kNumPart]).  Every thread of
 // the work-group calls it (it holds barriers).
-template <int NT>
+template <int NT, int NR>
 __device__ __forceinline__ void group_sums(const double* part, uint32_t stride, uint32_t npart, uint32_t g0,
                                            uint32_t G, double* wsum, double* sg)
 {
@@ -361,36 +384,36 @@ __device__ __forceinline__ void group_sums(const double* part, uint32_t stride, 
     const uint32_t g = g0 + t / (uint32_t)kGroupThreads;
     if (g < G) {                       // uniform over each 256 threads (whole waves)
         const uint32_t r0 = g * (uint32_t)kGroupRecords + tl;
-        double q[4][kNumPart];
+        double q[4][NR];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t r = r0 + (uint32_t)(u * kGroupThreads);
             const double* p = part + (r < npart ? r : 0u);     // record 0 always exists
 #pragma unroll
-            for (int e = 0; e < kNumPart; ++e) q[u][e] = p[(size_t)e * stride];
+            for (int e = 0; e < NR; ++e) q[u][e] = p[(size_t)e * stride];
         }
         // a record past the end adds +0.0, which changes no sum (no partial
         // sum here is ever -0.0), so the loads need no branch
-        double v[kNumPart];
+        double v[NR];
 #pragma unroll
-        for (int e = 0; e < kNumPart; ++e) v[e] = 0.0;
+        for (int e = 0; e < NR; ++e) v[e] = 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const bool in = r0 + (uint32_t)(u * kGroupThreads) < npart;
 #pragma unroll
-            for (int e = 0; e < kNumPart; ++e) v[e] += in ? q[u][e] : 0.0;
+            for (int e = 0; e < NR; ++e) v[e] += in ? q[u][e] : 0.0;
         }
         // all wave sums first, then one branch for the stores
 #pragma unroll
-        for (int e = 0; e < kNumPart; ++e) v[e] = wave_sum(v[e]);
+        for (int e = 0; e < NR; ++e) v[e] = wave_sum(v[e]);
         if ((t & 63u) == 0) {
 #pragma unroll
-            for (int e = 0; e < kNumPart; ++e) wsum[(t >> 6) * kNumPart + e] = v[e];
+            for (int e = 0; e < NR; ++e) wsum[(t >> 6) * kNumPart + e] = v[e];
         }
     }
     __syncthreads();
-    if (t < (uint32_t)(PG * kNumPart)) {
-        const uint32_t j = t / (uint32_t)kNumPart, e = t % (uint32_t)kNumPart;
+    if (t < (uint32_t)(PG * NR)) {
+        const uint32_t j = t / (uint32_t)NR, e = t % (uint32_t)NR;
         if (g0 + j < G) {
             double x = 0.0;
             for (int w = 0; w < kGroupThreads / 64; ++w)
@@ -442,19 +465,23 @@ __device__ __forceinline__ void finalize_body(DevState* st, const double* part, 
     }
     if (fin & kFinObs) {
         const uint32_t G = (npart + (uint32_t)kGroupRecords - 1u) / (uint32_t)kGroupRecords;
+        const bool torque = (fin & kFinTorque) != 0;
+        const uint32_t nrows = torque ? (uint32_t)kTorqueRows : (uint32_t)kObsRows;
         if (l2 != nullptr) {
             if (t < (uint32_t)kNumPart) {
                 double x = 0.0;
-                for (uint32_t g = 0; g < G; ++g) x += l2[(size_t)g * kNumPart + t];
+                if (t < nrows)
+                    for (uint32_t g = 0; g < G; ++g) x += l2[(size_t)g * kNumPart + t];
                 tot[t] = x;
             }
         } else {
             // rounds of NT / 256 groups formed side by side, added in order
             constexpr uint32_t PG = NT / kGroupThreads;
-            double run = 0.0;          // threads 0..kNumPart-1: the running total
+            double run = 0.0;          // threads 0..nrows-1: the running total
             for (uint32_t g0 = 0; g0 < G; g0 += PG) {
-                group_sums<NT>(part, stride, npart, g0, G, wsum, sg);
-                if (t < (uint32_t)kNumPart)
+                if (torque) group_sums<NT, kTorqueRows>(part, stride, npart, g0, G, wsum, sg);
+                else group_sums<NT, kObsRows>(part, stride, npart, g0, G, wsum, sg);
+                if (t < nrows)
                     for (uint32_t j = 0; j < PG && g0 + j < G; ++j) run += sg[j * kNumPart + t];
             }
             if (t < (uint32_t)kNumPart) tot[t] = run;
@@ -965,7 +992,7 @@ __device__ __forceinline__ void pass_tile(const KArgs<R>& a, const uint32_t zc, 
     if constexpr (DEEP) march2<R, C, OBS, SPT, HALO, MASK>(a, g, x, nacc, acc);
     else march1<R, C, OBS, SPT, HALO, MASK>(a, g, x, nacc, acc);
     // LDS is free after the last barrier of the march
-    block_end<R, OBS>(a, C, b, nacc, acc, reinterpret_cast<double*>(smem));
+    block_end<R, OBS, false>(a, C, b, nacc, acc, reinterpret_cast<double*>(smem));
 }
 
 // The depth-two FP32 variants with up to two sites per thread are held to
