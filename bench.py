@@ -572,7 +572,7 @@ def main():
                 "kernel": "pair_kernel<float> (one colour's pair moves, 128^3)",
                 "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(pair_ms, 5),
                 "note": "the 2 M-spin working set sits in the Infinity Cache; the pass is bound neither by "
-                        "HBM bandwidth nor by instruction issue (VALU busy about 45 % of the pass, waiting on "
+                        "HBM bandwidth nor by instruction issue (VALU busy about half of the pass, waiting on "
                         "memory 12-13 % of the time; a quarter fewer instructions, interleaved pair chains, "
                         "more waves or no work-group barriers did not make it faster); its random partner "
                         "line and its write-backs cost about 2.4 us each"}
