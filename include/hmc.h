@@ -233,8 +233,9 @@ int hmc_set_state(hmc_lattice* L, const void* host_buf, size_t bytes);
  * [1, 1024].  The spins produced do not depend on the shape (random
  * numbers are keyed by site); reduction orders, and so the last bits of
  * the observables, do.  Default: 2 sites per thread (1 where the LDS
- * window of 512 sites would not fit) and z_chunk 16, or 8 for FP32 lattices
- * whose spins exceed 256 MiB (the march that loads two planes ahead).
+ * window of 512 sites would not fit) and z_chunk 16; lattices whose spins
+ * exceed 256 MiB (the march that loads two planes ahead) take 8 at FP32
+ * and 32 at FP64.
  * Errors: HMC_EINVAL. */
 int hmc_set_launch(hmc_lattice* L, int32_t sites_per_thread, int32_t z_chunk);
 int hmc_get_launch(const hmc_lattice* L, int32_t* sites_per_thread, int32_t* z_chunk);

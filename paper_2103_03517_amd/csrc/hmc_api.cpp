@@ -319,14 +319,17 @@ int hmc_init_lattice(const hmc_params* p, void* dev_ws, size_t ws_bytes, void* h
         L->c1f[th] = (float)L->c1d[th];
     }
     // default launch shape: 512 in-plane sites per work-group, narrowed to
-    // 256 sites when the LDS window would exceed its budget; 16 planes, or 8
-    // for FP32 spins that stream from HBM (the depth-two march): shorter
-    // slabs give more work-groups to spread over the chip (measured on
-    // MI355X at 384^3 and 464^3 FP32: 2.9 % and 1.9 % faster passes), and
-    // the finalize folds the extra records in parallel.  FP64 keeps 16
-    // (256^3 FP64: 63.7 G updates/s with 16 planes, 60.4 with 8).
+    // 256 sites when the LDS window would exceed its budget; 16 planes while
+    // the spins fit the last-level cache.  Spins that stream from HBM (the
+    // depth-two march) take 8 planes at FP32: shorter slabs give more
+    // work-groups to spread over the chip (measured on MI355X at 384^3 and
+    // 464^3 FP32: 2.9 % and 1.9 % faster passes), and the finalize folds the
+    // extra records in parallel.  At FP64 they take 32: fewer slab ends to
+    // re-read (measured on MI355X: 256^3 63.9-64.3 against 62.8-63.0 G
+    // updates/s with 16 planes and 60.4 with 8; 384^3 61.0-61.4 against
+    // 60.3-60.7).
     if (hmc::pass_lds_bytes(p->precision, d.hx, L->spt) > hmc::kMaxLds) L->spt = 1;
-    if (p->precision == 32 && hmc::pass_deep(d)) L->zc = 8;
+    if (hmc::pass_deep(d)) L->zc = p->precision == 32 ? 8 : 32;
     memset(&L->init_state, 0, sizeof(L->init_state));
     L->init_state.theta = p->theta0_deg;
 
