@@ -373,6 +373,36 @@ def test_mixed_standard_and_constrained(H, O):
         assert g.observables()["theta_deg"] == o.counters()[0]
 
 
+@pytest.mark.parametrize("shape", [(8, 8, 4), (96, 96, 64)])
+def test_mixed_sampled_sweeps_fp64_observables(H, O, shape):
+    """Sampled standard and constrained sweeps on one lattice: constrained
+    passes reduce the torque as well, standard passes only M and the
+    energies, and neither reads what the other left in the work-group
+    records.  Spins every round and all accumulated observables against the
+    reference (the larger lattice's standard passes write two groups of
+    records, folded in parallel)."""
+    _say("mixed sampled", shape)
+    kw = dict(J=1.0, Ku=0.04, Kc=0.06, h=(0.0, 0.01, 0.0), seed=21, instance=3)
+    g, o = _pair(H, O, shape, kw, init_dir=(1, 1, 1))
+    if shape[0] > 8:
+        g.set_launch(1, 1)      # 1152 records per standard pass: two groups, folded in parallel
+    eC = np.array([0.3, 0.5, 0.8]) / np.linalg.norm([0.3, 0.5, 0.8])
+    for it in range(3):
+        g.constrained_sweep(0.7, eC, 2, sample=True)
+        o.constrained_sweep(0.7, eC, 2, sample=True)
+        g.sweep(0.7, 2, sample=True)
+        o.sweep(0.7, 2, sample=True)
+        assert np.max(np.abs(g.spins() - o.spins())) <= TOL
+    a, b = g.observables(), o.observables(0.7)
+    assert a["samples"] == b["samples"] == 12 and a["torque_samples"] == 6
+    assert np.allclose(a["mean_m"], b["mean_m"], rtol=1e-11, atol=1e-13)
+    assert np.allclose(a["mean_E"], b["mean_E"], rtol=1e-11, atol=1e-13)
+    assert abs(a["mean_Eanis"] - b["mean_Eanis"]) < 1e-12
+    assert np.allclose(a["mean_torque"], b["mean_torque"], rtol=1e-9, atol=1e-12)
+    assert np.allclose(a["M"], b["M"], rtol=1e-11, atol=1e-9)
+    assert np.allclose(a["E"], b["E"], rtol=1e-11, atol=1e-9)
+
+
 @pytest.mark.parametrize("precision", [64, 32])
 def test_launch_shape_does_not_change_spins(H, precision):
     _say("launch shapes", precision)
