@@ -375,6 +375,8 @@ def main():
                     help="run a few 256^3 FP32 sweeps and nothing else (for counter runs)")
     ap.add_argument("--profile-deep", action="store_true",
                     help="only 60 sampled 384^3 FP32 sweeps (the two-plane march), for rocprofv3")
+    ap.add_argument("--profile-fp64", action="store_true",
+                    help="20 sampled 256^3 FP64 sweeps in the default launch (for rocprofv3), no JSON line")
     ap.add_argument("--profile-constrained", action="store_true",
                     help="run a few 128^3 FP32 constrained sweeps and nothing else")
     ap.add_argument("--profile-batch", action="store_true",
@@ -415,6 +417,14 @@ def main():
         g.sweep(1.0, 60, sample=True)
         torch.cuda.synchronize()
         log(f"profile-deep: 60 sampled 384^3 FP32 sweeps (120 colour passes, two planes of look-ahead, "
+            f"launch shape {g.get_launch()})")
+        return
+    if args.profile_fp64:
+        g = H.Lattice(256, 256, 256, precision=64, J=1.0, Ku=0.005, eu=(0, 0, 1), seed=7,
+                      init="random")
+        g.sweep(1.0, 20, sample=True)
+        torch.cuda.synchronize()
+        log(f"profile-fp64: 20 sampled 256^3 FP64 sweeps (40 colour passes, look-ahead {g.get_prefetch()}, "
             f"launch shape {g.get_launch()})")
         return
     if args.serve_only:
